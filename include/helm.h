@@ -1,0 +1,186 @@
+/*
+ * helm.h -- C ABI of the MI355X fast-diagonalization Helmholtz/Laplace solver.
+ *
+ * The library solves   (sigma I - Lap_h) u = f   on a 3D tensor-product grid, where
+ * Lap_h is the second-order finite-volume Laplacian (Vitoshkin & Gelfgat, Section 3,
+ * eqs. 23-29): per axis the 1D operator A_d = -D_dd is eigen-decomposed once on the
+ * host (eq. 24), and every solve transforms the right-hand side with E_d^{-1} along
+ * x, y and z, divides by lambda_x(a) + lambda_y(b) + lambda_z(c) + sigma (eqs. 26-27)
+ * and transforms back with E_d (eq. 29).  The TPT variant replaces the z-direction
+ * eigen-transforms by one tridiagonal (Thomas) solve per (a, b) line (end of Section 3).
+ *
+ * Sign convention: the paper writes the Helmholtz operator as Lap + a I (eq. 27) and
+ * H = Lap - I/dt (Section 2); here sigma = -a = 1/dt and eigenvalues lambda = -Lambda >= 0.
+ *
+ * Memory layout of every grid function: contiguous float64 [nrhs][nz][ny][nx], x fastest.
+ * Pointers named f, u, p, b, Hu are DEVICE pointers; grid faces and sigma arrays are HOST
+ * pointers.  `stream` is a hipStream_t (NULL = the default stream).  All device work is
+ * enqueued on `stream` without host synchronization, except where a call says otherwise.
+ *
+ * Errors: every call returns helm_status; no C++ exception crosses this boundary.
+ * Thread safety: distinct plans may be used concurrently; one plan may be used by
+ * several threads at once provided each call has its own workspace and stream.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HELM_OK = 0,
+  HELM_EINVAL = 1,        /* bad argument: NULL pointer, size < 2, non-increasing faces, bad enum */
+  HELM_ESINGULAR = 2,     /* a denominator lambda_x+lambda_y+lambda_z+sigma is (numerically) zero
+                             outside the all-Neumann null mode */
+  HELM_ENOMEM = 3,        /* host or device allocation failed */
+  HELM_EDEVICE = 4,       /* a HIP runtime call failed (including an asynchronous fault surfaced
+                             at a synchronization point) */
+  HELM_ENOTCONVERGED = 5, /* iterative refinement or GMRES did not reach its tolerance; the output
+                             holds the best iterate */
+  HELM_ENONFINITE = 6     /* NaN or Inf detected in a refinement norm */
+} helm_status;
+
+/* Boundary condition of one wall (homogeneous). */
+enum { HELM_DIRICHLET = 0, HELM_NEUMANN = 1 };
+/* Location of the unknowns along one axis: cell centres, or interior faces (a staggered
+ * velocity component along its own direction, with wall value 0 on the wall faces). */
+enum { HELM_CELL = 0, HELM_FACE = 1 };
+/* Arithmetic of the mode products.  The *_IR forms run the products in the low precision
+ * and recover FP64 accuracy by iterative refinement with an FP64 7-point residual. */
+enum { HELM_FP64 = 0, HELM_FP32 = 1, HELM_BF16 = 2, HELM_FP32_IR = 3, HELM_BF16_IR = 4 };
+/* TPF: eigen-transforms along x, y, z (eq. 29).  TPT_Z: eigen-transforms along x, y and
+ * one Thomas tridiagonal solve per z line (end of Section 3). */
+enum { HELM_TPF = 0, HELM_TPT_Z = 1 };
+/* All-Neumann Laplace null mode (eq. 28 discussion): PROJECT sets the zero mode of the
+ * solution to 0 (the right-hand side is projected onto the range and u has zero
+ * volume-weighted mean); PAPER_EQ28 replaces the zero denominator by 1 as in eq. 28. */
+enum { HELM_NULL_PROJECT = 0, HELM_NULL_PAPER_EQ28 = 1 };
+
+typedef struct {
+  int n[3];                 /* cells per axis (x, y, z); each >= 2 (>= 3 for HELM_FACE) */
+  const double* faces[3];   /* host, n[d] + 1 strictly increasing face coordinates; copied */
+  int loc[3];               /* HELM_CELL or HELM_FACE per axis */
+} helm_grid;
+
+typedef struct {
+  int lo[3];                /* HELM_DIRICHLET / HELM_NEUMANN at the low wall of each axis */
+  int hi[3];                /* ... at the high wall */
+} helm_bc;
+
+typedef struct {
+  int precision;            /* HELM_FP64 (default) ... HELM_BF16_IR */
+  int method;               /* HELM_TPF (default) or HELM_TPT_Z */
+  double ir_tol;            /* refinement stops when max|du| <= ir_tol * max|u| (default 1e-11) */
+  int max_sweeps;           /* refinement sweep limit, including the first solve (default 12) */
+  int null_mode;            /* HELM_NULL_PROJECT (default) or HELM_NULL_PAPER_EQ28 */
+} helm_opts;
+
+typedef struct {
+  int sweeps;               /* low-precision solves performed (1 for the plain precisions) */
+  double last_correction;   /* max|du| / max|u| of the last refinement sweep (0 if none) */
+  int converged;            /* 1 if the refinement tolerance was met (always 1 without IR) */
+  int iterations;           /* GMRES iterations (pressure-matrix solve only) */
+  double residual;          /* final relative residual (pressure-matrix solve only) */
+} helm_info;
+
+typedef struct helm_plan helm_plan;
+typedef struct helm_pmat helm_pmat;
+
+/* Fills *opts with the defaults listed above. */
+void helm_default_opts(helm_opts* opts);
+
+/* Human-readable name of a status code (static string). */
+const char* helm_status_str(helm_status s);
+
+/* Builds a solve plan for (sigma I - Lap_h) u = f (eqs. 23-29).  Host work: 1D FV operators
+ * from the faces (Section 3, eq. 23), FP64 symmetric-tridiagonal eigen-decomposition of
+ * V^{-1/2} K V^{-1/2} per axis (eq. 24, done once), then one upload of E, E^{-1} (FP64,
+ * FP32, BF16), the eigenvalues and the 7-point coefficients to the current HIP device.
+ * opts may be NULL (defaults).  On success *out owns device memory until helm_destroy.
+ * Errors: EINVAL, ESINGULAR (sigma < 0 hits a zero denominator), ENOMEM, EDEVICE. */
+helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma,
+                       const helm_opts* opts, helm_plan** out);
+
+/* Bytes of device workspace helm_solve needs for nrhs right-hand sides. */
+helm_status helm_workspace_size(const helm_plan* plan, int nrhs, size_t* bytes);
+
+/* Solves for nrhs right-hand sides (1 <= nrhs <= 64).  f, u: device [nrhs][nz][ny][nx]
+ * float64; u may equal f only for the non-refined precisions (else EINVAL).
+ * sigma_per_rhs: host array of nrhs shifts overriding the plan's sigma, or NULL (the
+ * eigenbasis does not depend on sigma; only the denominators change).  ws: device
+ * workspace of at least helm_workspace_size bytes (256-byte aligned).  Without
+ * refinement the call is fully asynchronous on `stream`.  With refinement each sweep
+ * ends with one 16-byte device-to-host copy of the correction norms, so the call
+ * returns after the device work is done.  info (host, nullable) receives the sweep
+ * count and final correction.  Errors: EINVAL, ESINGULAR, ENOTCONVERGED (u holds the
+ * last iterate), ENONFINITE, EDEVICE. */
+helm_status helm_solve(helm_plan* plan, const double* f, double* u, int nrhs,
+                       const double* sigma_per_rhs, void* ws, void* stream, helm_info* info);
+
+/* Hu = (sigma I - Lap_h) u with the FP64 7-point operator (the Kronecker sum of eq. 29),
+ * device pointers [nrhs][nz][ny][nx]; asynchronous.  Hu must not alias u. */
+helm_status helm_apply(const helm_plan* plan, const double* u, double* Hu, int nrhs,
+                       const double* sigma_per_rhs, void* stream);
+
+/* Host copies of one axis' eigenpairs: lam[n], E[n*n] and Einv[n*n] row-major with
+ * E[i*n + a] = component i of eigenvector a, so that A_d = E diag(lam) Einv.  Any output
+ * pointer may be NULL.  n here is the number of unknowns on that axis. */
+helm_status helm_get_eigen(const helm_plan* plan, int axis, int* n, double* lam, double* E,
+                           double* Einv);
+
+/* Releases the plan and its device memory (synchronizes the device first). */
+void helm_destroy(helm_plan* plan);
+
+/* Pressure-Laplacian plan used as the pressure-matrix preconditioner (Section 2 and the
+ * Neumann case of Section 3, eq. 28): cell-centred, all walls Neumann, sigma = 0.
+ * Equivalent to helm_setup with those arguments and null_mode from opts. */
+helm_status helm_pressure_setup(const helm_grid* grid, const helm_opts* opts, helm_plan** out);
+
+/* Solves -Lap_h p = f - mean_V(f) and returns p with zero volume-weighted mean. */
+helm_status helm_pressure_solve(helm_plan* plan, const double* f, double* p, int nrhs, void* ws,
+                                void* stream, helm_info* info);
+
+/* Pressure matrix C of eq. 9 on a MAC grid: C p = -sum_d Div_d H_d^{-1} Grad_d p with
+ * H_d = (1/tau) I - Lap_h on the d-velocity grid (no-slip walls) and no pressure
+ * boundary values.  p_grid gives the pressure cells (loc ignored); the three velocity
+ * plans use opts->precision for their Helmholtz solves; the preconditioner is the
+ * pressure Laplacian (the Chorin limit of C, end of Section 2).  Errors as helm_setup. */
+helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, const helm_opts* opts,
+                               helm_pmat** out);
+
+/* Workspace bytes for helm_pmatrix_apply / helm_pmatrix_solve with restart length m. */
+helm_status helm_pmatrix_workspace_size(const helm_pmat* pm, int restart, size_t* bytes);
+
+/* y = C p (one right-hand side), device pointers over the pressure grid. */
+helm_status helm_pmatrix_apply(helm_pmat* pm, const double* p, double* y, void* ws, void* stream);
+
+/* Solves C p = b by right-preconditioned flexible GMRES(restart) with the pressure
+ * Laplacian as preconditioner (the Krylov inverse of C in Section 2).  b must have zero
+ * volume-weighted mean; p is returned with zero volume-weighted mean.  Stops when the
+ * relative residual ||b - C p|| / ||b|| <= tol or after max_it iterations (ENOTCONVERGED).
+ * use_precond = 0 runs plain GMRES (for comparison).  Synchronizes once per iteration. */
+helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double* p, double tol, int max_it,
+                               int restart, int use_precond, void* ws, void* stream,
+                               helm_info* info);
+
+void helm_pmatrix_destroy(helm_pmat* pm);
+
+/* Host-only helpers (no device needed), for checking the setup stage on any machine. */
+/* 1D operator of one axis: lower/diag/upper rows of A = V^{-1} K (each of length m, the
+ * number of unknowns) and the control-volume widths vol[m].  Returns m in *m_out. */
+helm_status helm_host_operator_1d(int n, const double* faces, int loc, int bc_lo, int bc_hi,
+                                  int* m_out, double* lower, double* diag, double* upper,
+                                  double* vol);
+/* FP64 eigen-decomposition of that operator (eq. 24): lam[m] ascending, E and Einv m*m
+ * row-major as in helm_get_eigen. */
+helm_status helm_host_eigen_1d(int n, const double* faces, int loc, int bc_lo, int bc_hi,
+                               int* m_out, double* lam, double* E, double* Einv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

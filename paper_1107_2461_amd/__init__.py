@@ -1,0 +1,254 @@
+"""MI355X fast-diagonalization Helmholtz/Laplace solver (Vitoshkin & Gelfgat, Section 3).
+
+Thin Python binding over libhelm.so (include/helm.h): argument marshalling only.  Every
+step of a solve runs in the library's HIP kernels; PyTorch supplies device memory and
+streams.  There is no CPU fallback: a missing library raises.
+
+    from paper_1107_2461_amd import Plan
+    plan = Plan(faces=(fx, fy, fz), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), sigma=10.0)
+    u = plan.solve(f)          # f: float64 CUDA tensor [nrhs, nz, ny, nx]
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BF16, BF16_IR, CELL, DIRICHLET, FACE, FP32, FP32_IR, FP64, NEUMANN, NULL_PAPER_EQ28,
+                   NULL_PROJECT, TPF, TPT_Z, HelmError, check, load)
+
+__all__ = ["Plan", "PressureMatrix", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
+           "NEUMANN", "CELL", "FACE", "FP64", "FP32", "BF16", "FP32_IR", "BF16_IR", "TPF", "TPT_Z",
+           "NULL_PROJECT", "NULL_PAPER_EQ28"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _grid(faces, loc):
+    arrs = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
+    g = _lib.HelmGrid()
+    for d in range(3):
+        g.n[d] = len(arrs[d]) - 1
+        g.faces[d] = arrs[d].ctypes.data_as(_lib.DP)
+        g.loc[d] = int(loc[d])
+    return g, arrs
+
+
+def _opts(precision, method, ir_tol, max_sweeps, null_mode):
+    o = _lib.HelmOpts()
+    load().helm_default_opts(C.byref(o))
+    o.precision = _lib.PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
+    o.method = _lib.METHODS.get(method, method) if isinstance(method, str) else int(method)
+    if ir_tol is not None:
+        o.ir_tol = float(ir_tol)
+    if max_sweeps is not None:
+        o.max_sweeps = int(max_sweeps)
+    o.null_mode = int(null_mode)
+    return o
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A solve plan for (sigma I - Lap_h) u = f (helm_setup)."""
+
+    def __init__(self, faces, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, sigma=0.0, loc=(CELL,) * 3,
+                 precision="fp64", method="tpf", ir_tol=None, max_sweeps=None, null_mode=NULL_PROJECT,
+                 pressure=False):
+        lib = load()
+        g, self._faces = _grid(faces, loc)
+        opts = _opts(precision, method, ir_tol, max_sweeps, null_mode)
+        h = C.c_void_p()
+        if pressure:
+            check(lib.helm_pressure_setup(C.byref(g), C.byref(opts), C.byref(h)), "helm_pressure_setup")
+        else:
+            bc = _lib.HelmBC()
+            for d in range(3):
+                bc.lo[d] = int(bc_lo[d])
+                bc.hi[d] = int(bc_hi[d])
+            check(lib.helm_setup(C.byref(g), C.byref(bc), float(sigma), C.byref(opts), C.byref(h)), "helm_setup")
+        self._h = h
+        self.sigma = 0.0 if pressure else float(sigma)
+        self.pressure = pressure
+        self.shape_xyz = tuple(self.eigen(d)[0].shape[0] for d in range(3))
+        self._ws = {}
+        self.last_info = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                load().helm_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, nrhs):
+        n = C.c_size_t()
+        check(load().helm_workspace_size(self._h, int(nrhs), C.byref(n)), "helm_workspace_size")
+        return n.value
+
+    def workspace(self, nrhs, device=None):
+        torch = _torch()
+        key = (nrhs, device)
+        ws = self._ws.get(key)
+        if ws is None:
+            ws = torch.empty(max(self.workspace_bytes(nrhs), 1) + 256, dtype=torch.uint8,
+                             device=device or "cuda")
+            self._ws[key] = ws
+        return ws
+
+    @staticmethod
+    def _aligned(ws):
+        p = ws.data_ptr()
+        return C.c_void_p((p + 255) // 256 * 256)
+
+    def solve(self, f, out=None, sigma=None, stream=None, workspace=None):
+        """u = H^{-1} f for f: float64 CUDA tensor [nrhs, nz, ny, nx] (or [nz, ny, nx])."""
+        torch = _torch()
+        squeeze = f.dim() == 3
+        f4 = f.unsqueeze(0) if squeeze else f
+        if f4.dtype != torch.float64 or not f4.is_cuda or not f4.is_contiguous():
+            raise ValueError("f must be a contiguous float64 CUDA tensor")
+        nrhs = f4.shape[0]
+        if tuple(f4.shape[1:]) != self.shape_xyz[::-1]:
+            raise ValueError(f"f shape {tuple(f4.shape)} does not match the plan grid {self.shape_xyz[::-1]}")
+        u = torch.empty_like(f4) if out is None else (out.unsqueeze(0) if out.dim() == 3 else out)
+        ws = workspace if workspace is not None else self.workspace(nrhs, f4.device)
+        sig = None
+        if sigma is not None:
+            sarr = (C.c_double * nrhs)(*[float(s) for s in np.broadcast_to(np.asarray(sigma, float), (nrhs,))])
+            sig = C.cast(sarr, _lib.DP)
+        info = _lib.HelmInfo()
+        fn = load().helm_pressure_solve if self.pressure else load().helm_solve
+        if self.pressure:
+            st = fn(self._h, C.c_void_p(f4.data_ptr()), C.c_void_p(u.data_ptr()), nrhs, self._aligned(ws),
+                    _stream_ptr(stream), C.byref(info))
+        else:
+            st = fn(self._h, C.c_void_p(f4.data_ptr()), C.c_void_p(u.data_ptr()), nrhs, sig, self._aligned(ws),
+                    _stream_ptr(stream), C.byref(info))
+        self.last_info = dict(sweeps=info.sweeps, last_correction=info.last_correction,
+                              converged=bool(info.converged))
+        check(st, "helm_solve")
+        return u[0] if squeeze else u
+
+    def apply(self, u, sigma=None, stream=None):
+        """Hu with the FP64 7-point operator (helm_apply)."""
+        torch = _torch()
+        u4 = u.unsqueeze(0) if u.dim() == 3 else u
+        if u4.dtype != torch.float64 or not u4.is_cuda or not u4.is_contiguous():
+            raise ValueError("u must be a contiguous float64 CUDA tensor")
+        out = torch.empty_like(u4)
+        nrhs = u4.shape[0]
+        sig = None
+        if sigma is not None:
+            sarr = (C.c_double * nrhs)(*[float(s) for s in np.broadcast_to(np.asarray(sigma, float), (nrhs,))])
+            sig = C.cast(sarr, _lib.DP)
+        check(load().helm_apply(self._h, C.c_void_p(u4.data_ptr()), C.c_void_p(out.data_ptr()), nrhs, sig,
+                                _stream_ptr(stream)), "helm_apply")
+        return out[0] if u.dim() == 3 else out
+
+    def eigen(self, axis):
+        lib = load()
+        n = C.c_int()
+        check(lib.helm_get_eigen(self._h, axis, C.byref(n), None, None, None), "helm_get_eigen")
+        m = n.value
+        lam = np.empty(m)
+        E = np.empty((m, m))
+        Ei = np.empty((m, m))
+        check(lib.helm_get_eigen(self._h, axis, C.byref(n), lam.ctypes.data_as(_lib.DP), E.ctypes.data_as(_lib.DP),
+                                 Ei.ctypes.data_as(_lib.DP)), "helm_get_eigen")
+        return lam, E, Ei
+
+
+def host_operator_1d(faces, loc=CELL, bc_lo=DIRICHLET, bc_hi=DIRICHLET):
+    """Rows (lower, diag, upper) of A = V^{-1} K and control volumes, computed by the library's host code."""
+    lib = load()
+    fa = np.ascontiguousarray(np.asarray(faces, dtype=np.float64))
+    n = len(fa) - 1
+    out = [np.zeros(n) for _ in range(4)]
+    m = C.c_int()
+    check(lib.helm_host_operator_1d(n, fa.ctypes.data_as(_lib.DP), loc, bc_lo, bc_hi, C.byref(m),
+                                    *[o.ctypes.data_as(_lib.DP) for o in out]), "helm_host_operator_1d")
+    return tuple(o[:m.value] for o in out)
+
+
+def host_eigen_1d(faces, loc=CELL, bc_lo=DIRICHLET, bc_hi=DIRICHLET):
+    """(lam, E, Einv) of one axis from the library's host eigensolver."""
+    lib = load()
+    fa = np.ascontiguousarray(np.asarray(faces, dtype=np.float64))
+    n = len(fa) - 1
+    lam = np.zeros(n)
+    E = np.zeros(n * n)
+    Ei = np.zeros(n * n)
+    m = C.c_int()
+    check(lib.helm_host_eigen_1d(n, fa.ctypes.data_as(_lib.DP), loc, bc_lo, bc_hi, C.byref(m),
+                                 lam.ctypes.data_as(_lib.DP), E.ctypes.data_as(_lib.DP), Ei.ctypes.data_as(_lib.DP)),
+          "helm_host_eigen_1d")
+    mm = m.value
+    return lam[:mm], E[:mm * mm].reshape(mm, mm), Ei[:mm * mm].reshape(mm, mm)
+
+
+class PressureMatrix:
+    """Pressure matrix C of eq. 9 with FGMRES solve (helm_pmatrix_*)."""
+
+    def __init__(self, faces, tau, precision="fp64"):
+        lib = load()
+        g, self._faces = _grid(faces, (CELL,) * 3)
+        opts = _opts(precision, "tpf", None, None, NULL_PROJECT)
+        h = C.c_void_p()
+        check(lib.helm_pmatrix_setup(C.byref(g), float(tau), C.byref(opts), C.byref(h)), "helm_pmatrix_setup")
+        self._h = h
+        self.shape_xyz = tuple(len(f) - 1 for f in faces)
+        self._ws = {}
+        self.last_info = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                load().helm_pmatrix_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _workspace(self, restart, device):
+        torch = _torch()
+        ws = self._ws.get(restart)
+        if ws is None:
+            n = C.c_size_t()
+            check(load().helm_pmatrix_workspace_size(self._h, int(restart), C.byref(n)), "workspace")
+            ws = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+            self._ws[restart] = ws
+        return Plan._aligned(ws)
+
+    def apply(self, p, stream=None):
+        torch = _torch()
+        y = torch.empty_like(p)
+        check(load().helm_pmatrix_apply(self._h, C.c_void_p(p.data_ptr()), C.c_void_p(y.data_ptr()),
+                                        self._workspace(30, p.device), _stream_ptr(stream)), "helm_pmatrix_apply")
+        return y
+
+    def solve(self, b, tol=1e-10, max_it=500, restart=30, precondition=True, stream=None):
+        torch = _torch()
+        p = torch.empty_like(b)
+        info = _lib.HelmInfo()
+        st = load().helm_pmatrix_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(p.data_ptr()), float(tol),
+                                       int(max_it), int(restart), int(bool(precondition)),
+                                       self._workspace(restart, b.device), _stream_ptr(stream), C.byref(info))
+        self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK)
+        if st not in (_lib.HELM_OK, _lib.HELM_ENOTCONVERGED):
+            check(st, "helm_pmatrix_solve")
+        return p

@@ -1,0 +1,99 @@
+"""ctypes declarations of libhelm.so (include/helm.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhelm.so")
+
+HELM_OK, HELM_EINVAL, HELM_ESINGULAR, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOTCONVERGED, HELM_ENONFINITE = range(7)
+DIRICHLET, NEUMANN = 0, 1
+CELL, FACE = 0, 1
+FP64, FP32, BF16, FP32_IR, BF16_IR = range(5)
+TPF, TPT_Z = 0, 1
+NULL_PROJECT, NULL_PAPER_EQ28 = 0, 1
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp32_ir": FP32_IR, "bf16_ir": BF16_IR}
+METHODS = {"tpf": TPF, "tpt": TPT_Z}
+
+
+class HelmGrid(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("faces", C.POINTER(C.c_double) * 3), ("loc", C.c_int * 3)]
+
+
+class HelmBC(C.Structure):
+    _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3)]
+
+
+class HelmOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("method", C.c_int), ("ir_tol", C.c_double), ("max_sweeps", C.c_int),
+                ("null_mode", C.c_int)]
+
+
+class HelmInfo(C.Structure):
+    _fields_ = [("sweeps", C.c_int), ("last_correction", C.c_double), ("converged", C.c_int),
+                ("iterations", C.c_int), ("residual", C.c_double)]
+
+
+P = C.c_void_p
+DP = C.POINTER(C.c_double)
+IP = C.POINTER(C.c_int)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "helm_default_opts": (None, [C.POINTER(HelmOpts)]),
+    "helm_status_str": (C.c_char_p, [C.c_int]),
+    "helm_setup": (C.c_int, [C.POINTER(HelmGrid), C.POINTER(HelmBC), C.c_double, C.POINTER(HelmOpts),
+                             C.POINTER(P)]),
+    "helm_workspace_size": (C.c_int, [P, C.c_int, C.POINTER(C.c_size_t)]),
+    "helm_solve": (C.c_int, [P, P, P, C.c_int, DP, P, P, C.POINTER(HelmInfo)]),
+    "helm_apply": (C.c_int, [P, P, P, C.c_int, DP, P]),
+    "helm_get_eigen": (C.c_int, [P, C.c_int, IP, DP, DP, DP]),
+    "helm_destroy": (None, [P]),
+    "helm_pressure_setup": (C.c_int, [C.POINTER(HelmGrid), C.POINTER(HelmOpts), C.POINTER(P)]),
+    "helm_pressure_solve": (C.c_int, [P, P, P, C.c_int, P, P, C.POINTER(HelmInfo)]),
+    "helm_pmatrix_setup": (C.c_int, [C.POINTER(HelmGrid), C.c_double, C.POINTER(HelmOpts), C.POINTER(P)]),
+    "helm_pmatrix_workspace_size": (C.c_int, [P, C.c_int, C.POINTER(C.c_size_t)]),
+    "helm_pmatrix_apply": (C.c_int, [P, P, P, P, P]),
+    "helm_pmatrix_solve": (C.c_int, [P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P,
+                                     C.POINTER(HelmInfo)]),
+    "helm_pmatrix_destroy": (None, [P]),
+    "helm_host_operator_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
+    "helm_host_eigen_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP]),
+}
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libhelm.so (built in-tree by paper_1107_2461_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run `python -m paper_1107_2461_amd.build` "
+                           "(the HIP library is required; there is no fallback)")
+    lib = C.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        msg = load().helm_status_str(status).decode()
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+def check(status, what=""):
+    if status != HELM_OK:
+        raise HelmError(status, what)

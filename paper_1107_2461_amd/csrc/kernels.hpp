@@ -1,0 +1,94 @@
+// Launchers for the gfx950 kernels of the solve path.  Host code calls only these.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace helm {
+
+// Storage / compute types of the mode products.
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+// Epilogue of a mode product.
+enum Epi : int {
+  EPI_STORE = 0,   // Y = acc (converted to the output storage type)
+  EPI_DIVIDE = 1,  // Y = acc / (lam_x[a] + lam_y[b] + lam_z[c] + sigma[r]) in FP64 (eqs. 26-28)
+  EPI_ACCUM = 2    // u += acc in FP64, with per-RHS max|acc| and max|u| (refinement update)
+};
+
+constexpr int kMaxRhs = 64;
+
+struct EpiArgs {
+  const double* lamx = nullptr;   // eigenvalues of the x and y axes (divide epilogue)
+  const double* lamy = nullptr;
+  const double* lamz = nullptr;   // eigenvalues of the contracted (z) axis
+  int nx = 1;                     // x extent, to split a column index into (b, a)
+  int eq28 = 0;                   // zero denominator -> 1 (eq. 28) instead of projection
+  unsigned long long* norms = nullptr;  // [2 * nrhs]: max|du| bits, max|u| bits (accumulate)
+  long long rows_per_rhs = 1;     // rows of the x-mode matrix per RHS (accumulate)
+  int accum_zero = 0;             // accumulate into zero instead of the current u
+  double sigma[kMaxRhs];          // per-RHS shift
+};
+
+// Bytes of one swizzled operand matrix (rows x k padded to the kernel's blocking).
+size_t swizzled_bytes(Prec p, int K);
+// Host-side swizzle of a row-major K x K matrix M (M[a][i]) into the fragment layout the
+// mode-product kernels read; `out` must hold swizzled_bytes(p, K) bytes.
+void swizzle_operand(Prec p, int K, const double* M, void* out);
+
+// Left form (contraction along a strided axis):
+//   Y[s][a][n] = sum_i M[a][i] X[s][i][n],  s < S, a < K, n < Nn.
+hipError_t mode_left(Prec p, const void* Msw, int K, const void* X, Prec tin, void* Y, Prec tout,
+                     long long S, long long Nn, Epi epi, const EpiArgs& ep, hipStream_t st);
+
+// Right form (contraction along the contiguous axis):
+//   Y[m][a] = sum_i X[m][i] M[a][i],  m < Mrows, a < K.
+hipError_t mode_right(Prec p, const void* Msw, int K, const void* X, Prec tin, void* Y, Prec tout,
+                      long long Mrows, Epi epi, const EpiArgs& ep, hipStream_t st);
+
+// Batched Thomas solve along z (TPT, end of Section 3): for every RHS r and (b, a) line,
+// (K_z + c V_z) v = V_z g with c = lam_x[a] + lam_y[b] + sigma[r], in place on v (FP64).
+// The line (0, 0) is skipped when skip_null != 0.  chk: scratch of thomas_scratch_bytes.
+struct ThomasArgs {
+  const double* kdiag;   // K_z diagonal [nz]
+  const double* koff;    // K_z off-diagonal [nz - 1]
+  const double* vol;     // V_z [nz]
+  const double* lamx;
+  const double* lamy;
+  int nx, ny, nz, nrhs;
+  int skip_null;
+  double sigma[kMaxRhs];
+};
+size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs);
+hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st);
+
+// The one singular z line of an all-Neumann Laplace TPT solve: v = E_z diag(1/lam') E_z^{-1} g
+// on the (0, 0) line of every RHS, with 1/lam'_0 = 0 (projection) or 1 (eq. 28).
+hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const double* lamz,
+                       int nx, int ny, int nz, int nrhs, int eq28, hipStream_t st);
+
+// 7-point FP64 operator (Kronecker sum of the 1D rows plus sigma):
+//   mode 0: out = H u;  mode 1: out = f - H u (residual);  mode 2: out = f (u unused);
+//   stored as `tout`.
+struct StencilArgs {
+  const double* cx;   // [3 * nx]: lower, diag, upper rows of A_x
+  const double* cy;   // [3 * ny]
+  const double* cz;   // [3 * nz]
+  int nx, ny, nz, nrhs;
+  double sigma[kMaxRhs];
+};
+hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout,
+                   const StencilArgs& a, hipStream_t st);
+
+// Zero `n` 64-bit words (a fill kernel, safe under stream capture).
+hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st);
+// Volume-weighted mean removal per RHS: x -= sum(vol * x) * inv_volsum   (FP64, in place,
+// deterministic order).  scratch: nrhs * (kMeanBlocks + 1) doubles of device memory.
+constexpr int kMeanBlocks = 512;
+hipError_t remove_mean(double* x, const double* volx, const double* voly, const double* volz,
+                       int nx, int ny, int nz, int nrhs, double inv_volsum, double* scratch,
+                       hipStream_t st);
+
+}  // namespace helm

@@ -1,0 +1,550 @@
+// Solver driver and C ABI (include/helm.h).
+//
+// helm_setup builds the per-axis 1D operators and eigenpairs on the host (Section 3,
+// eqs. 23-24), uploads them once, and helm_solve sequences the device kernels:
+//   TPF   (eq. 29):  x-fwd -> y-fwd -> z-fwd + divide (eqs. 26-28) -> z-inv -> y-inv -> x-inv
+//   TPT_Z         :  x-fwd -> y-fwd -> Thomas along z -> y-inv -> x-inv
+// In the low-precision forms the products run in FP32 or BF16 and the result is refined:
+//   u = M^{-1} f;  repeat r = f - H u (FP64 7-point), u += M^{-1} r  until max|du| <= tol max|u|.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using namespace helm;
+
+namespace {
+
+// Device copy of one axis' operator and eigenbasis.  Shared between plans through a
+// reference-counted cache keyed by the axis definition (faces, location, walls, device).
+struct DevAxis {
+  Axis1D host;
+  int device = 0;
+  double* lam = nullptr;     // m eigenvalues
+  double* coef = nullptr;    // 3m: lower, diag, upper rows of A
+  double* kdiag = nullptr;   // m   (Thomas)
+  double* koff = nullptr;    // m-1 (Thomas)
+  double* vol = nullptr;     // m
+  double* E = nullptr;       // m*m row-major
+  double* Einv = nullptr;    // m*m row-major
+  void* sw[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][fwd, inv]
+  ~DevAxis() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    for (double* p : {lam, coef, kdiag, koff, vol, E, Einv})
+      if (p) (void)hipFree(p);
+    for (auto& pr : sw)
+      for (void* p : pr)
+        if (p) (void)hipFree(p);
+    (void)hipSetDevice(cur);
+  }
+};
+
+std::mutex g_cache_mu;
+std::map<std::string, std::weak_ptr<DevAxis>> g_cache;
+
+helm_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return HELM_OK;
+  if (e == hipErrorOutOfMemory) return HELM_ENOMEM;
+  return HELM_EDEVICE;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t count) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (count) e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+std::string axis_key(int n, const double* faces, int loc, int lo, int hi, int device) {
+  std::string k(reinterpret_cast<const char*>(faces), sizeof(double) * (n + 1));
+  k.push_back(static_cast<char>(loc));
+  k.push_back(static_cast<char>(lo));
+  k.push_back(static_cast<char>(hi));
+  k.append(reinterpret_cast<const char*>(&device), sizeof(int));
+  return k;
+}
+
+helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::shared_ptr<DevAxis>& out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
+  const std::string key = axis_key(n, faces, loc, lo, hi, dev);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      out = it->second.lock();
+      if (out) return HELM_OK;
+    }
+  }
+  auto ax = std::make_shared<DevAxis>();
+  ax->device = dev;
+  Axis1D& h = ax->host;
+  if (!build_operator_1d(n, faces, loc, lo, hi, h).empty()) return HELM_EINVAL;
+  if (h.m > 512) return HELM_EINVAL;
+  if (!eigen_1d(h).empty()) return HELM_EINVAL;
+  const int m = h.m;
+  std::vector<double> coef(3 * m);
+  for (int i = 0; i < m; ++i) {
+    coef[3 * i] = h.lower[i];
+    coef[3 * i + 1] = h.diag[i];
+    coef[3 * i + 2] = h.upper[i];
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&ax->lam, h.lam.data(), m);
+  if (e == hipSuccess) e = upload(&ax->coef, coef.data(), coef.size());
+  if (e == hipSuccess) e = upload(&ax->kdiag, h.k_diag.data(), m);
+  if (e == hipSuccess) e = upload(&ax->koff, h.k_off.data(), h.k_off.size());
+  if (e == hipSuccess) e = upload(&ax->vol, h.vol.data(), m);
+  if (e == hipSuccess) e = upload(&ax->E, h.E.data(), h.E.size());
+  if (e == hipSuccess) e = upload(&ax->Einv, h.Einv.data(), h.Einv.size());
+  for (int p = 0; p < 3 && e == hipSuccess; ++p) {
+    const Prec pr = static_cast<Prec>(p);
+    const size_t bytes = swizzled_bytes(pr, m);
+    std::vector<unsigned char> buf(bytes);
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+      swizzle_operand(pr, m, dir == 0 ? h.Einv.data() : h.E.data(), buf.data());
+      e = upload(reinterpret_cast<unsigned char**>(&ax->sw[p][dir]), buf.data(), bytes);
+    }
+  }
+  if (e != hipSuccess) return from_hip(e);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      auto existing = it->second.lock();
+      if (existing) {
+        out = existing;
+        return HELM_OK;
+      }
+    }
+    g_cache[key] = ax;
+  }
+  out = ax;
+  return HELM_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct helm_plan {
+  std::shared_ptr<DevAxis> ax[3];
+  int m[3] = {0, 0, 0};   // unknowns per axis
+  double sigma = 0.0;
+  helm_opts opts{};
+  bool all_neumann = false;
+  int device = 0;
+  unsigned long long* host_norms = nullptr;  // pinned, 2 * kMaxRhs
+  std::mutex mu;                             // guards host_norms
+  ~helm_plan() {
+    if (host_norms) (void)hipHostFree(host_norms);
+  }
+  long long npts() const { return static_cast<long long>(m[0]) * m[1] * m[2]; }
+  bool refined() const { return opts.precision == HELM_FP32_IR || opts.precision == HELM_BF16_IR; }
+  Prec prec() const {
+    switch (opts.precision) {
+      case HELM_FP32:
+      case HELM_FP32_IR: return P_F32;
+      case HELM_BF16:
+      case HELM_BF16_IR: return P_BF16;
+      default: return P_F64;
+    }
+  }
+};
+
+extern "C" {
+
+void helm_default_opts(helm_opts* o) {
+  if (!o) return;
+  o->precision = HELM_FP64;
+  o->method = HELM_TPF;
+  o->ir_tol = 1e-11;
+  o->max_sweeps = 12;
+  o->null_mode = HELM_NULL_PROJECT;
+}
+
+const char* helm_status_str(helm_status s) {
+  switch (s) {
+    case HELM_OK: return "HELM_OK";
+    case HELM_EINVAL: return "HELM_EINVAL: invalid argument";
+    case HELM_ESINGULAR: return "HELM_ESINGULAR: zero denominator outside the Neumann null mode";
+    case HELM_ENOMEM: return "HELM_ENOMEM: out of memory";
+    case HELM_EDEVICE: return "HELM_EDEVICE: HIP runtime error";
+    case HELM_ENOTCONVERGED: return "HELM_ENOTCONVERGED: tolerance not reached";
+    case HELM_ENONFINITE: return "HELM_ENONFINITE: NaN or Inf encountered";
+  }
+  return "unknown helm_status";
+}
+
+helm_status helm_host_operator_1d(int n, const double* faces, int loc, int bc_lo, int bc_hi, int* m_out,
+                                  double* lower, double* diag, double* upper, double* vol) {
+  Axis1D ax;
+  if (!build_operator_1d(n, faces, loc, bc_lo, bc_hi, ax).empty()) return HELM_EINVAL;
+  if (m_out) *m_out = ax.m;
+  if (lower) std::copy(ax.lower.begin(), ax.lower.end(), lower);
+  if (diag) std::copy(ax.diag.begin(), ax.diag.end(), diag);
+  if (upper) std::copy(ax.upper.begin(), ax.upper.end(), upper);
+  if (vol) std::copy(ax.vol.begin(), ax.vol.end(), vol);
+  return HELM_OK;
+}
+
+helm_status helm_host_eigen_1d(int n, const double* faces, int loc, int bc_lo, int bc_hi, int* m_out, double* lam,
+                               double* E, double* Einv) {
+  Axis1D ax;
+  if (!build_operator_1d(n, faces, loc, bc_lo, bc_hi, ax).empty()) return HELM_EINVAL;
+  if (!eigen_1d(ax).empty()) return HELM_EINVAL;
+  if (m_out) *m_out = ax.m;
+  if (lam) std::copy(ax.lam.begin(), ax.lam.end(), lam);
+  if (E) std::copy(ax.E.begin(), ax.E.end(), E);
+  if (Einv) std::copy(ax.Einv.begin(), ax.Einv.end(), Einv);
+  return HELM_OK;
+}
+
+static bool valid_opts(const helm_opts& o) {
+  if (o.precision < HELM_FP64 || o.precision > HELM_BF16_IR) return false;
+  if (o.method != HELM_TPF && o.method != HELM_TPT_Z) return false;
+  if (o.null_mode != HELM_NULL_PROJECT && o.null_mode != HELM_NULL_PAPER_EQ28) return false;
+  if (!(o.ir_tol > 0.0) || o.max_sweeps < 1) return false;
+  // The Thomas path runs in FP64 only.
+  if (o.method == HELM_TPT_Z && o.precision != HELM_FP64) return false;
+  return true;
+}
+
+// Is some denominator lam_x + lam_y + lam_z + sigma numerically zero, other than the exact
+// all-Neumann null mode?  Only reachable with sigma < 0 (all eigenvalues are >= 0).
+static bool has_zero_denominator(const helm_plan* p, double sigma) {
+  if (sigma >= 0.0) return false;
+  const auto& lx = p->ax[0]->host.lam;
+  const auto& ly = p->ax[1]->host.lam;
+  const auto& lz = p->ax[2]->host.lam;
+  const double scale = lx.back() + ly.back() + lz.back() + std::fabs(sigma);
+  for (double c : lz)
+    for (double b : ly)
+      for (double a : lx)
+        if (std::fabs(a + b + c + sigma) <= 1e-13 * scale) return true;
+  return false;
+}
+
+helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, const helm_opts* opts,
+                       helm_plan** out) {
+  if (!grid || !bc || !out) return HELM_EINVAL;
+  *out = nullptr;
+  if (!std::isfinite(sigma)) return HELM_EINVAL;
+  helm_opts o;
+  helm_default_opts(&o);
+  if (opts) o = *opts;
+  if (!valid_opts(o)) return HELM_EINVAL;
+  std::unique_ptr<helm_plan> p(new (std::nothrow) helm_plan());
+  if (!p) return HELM_ENOMEM;
+  p->opts = o;
+  p->sigma = sigma;
+  if (hipGetDevice(&p->device) != hipSuccess) return HELM_EDEVICE;
+  bool alln = true;
+  for (int d = 0; d < 3; ++d) {
+    if (!grid->faces[d]) return HELM_EINVAL;
+    const helm_status s = get_axis(grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d], p->ax[d]);
+    if (s != HELM_OK) return s;
+    p->m[d] = p->ax[d]->host.m;
+    alln = alln && p->ax[d]->host.null_mode;
+  }
+  p->all_neumann = alln;
+  if (has_zero_denominator(p.get(), sigma)) return HELM_ESINGULAR;
+  if (hipHostMalloc(reinterpret_cast<void**>(&p->host_norms), 2 * kMaxRhs * sizeof(unsigned long long)) !=
+      hipSuccess)
+    return HELM_ENOMEM;
+  *out = p.release();
+  return HELM_OK;
+}
+
+// Workspace layout (each region 256-byte aligned):
+//   FP64:  W    nrhs*P doubles         (+ Thomas checkpoints for TPT_Z)
+//   low :  L1, L2  nrhs*P low-precision values each, norms 2*nrhs u64
+static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t* off_a, size_t* off_b,
+                             size_t* off_norms) {
+  const size_t P = static_cast<size_t>(p->npts()) * nrhs;
+  size_t t = 0;
+  if (p->prec() == P_F64) {
+    *off_a = 0;
+    t = align_up(P * 8, 256);
+    *off_b = t;
+    if (p->opts.method == HELM_TPT_Z) t += align_up(thomas_scratch_bytes(p->m[0], p->m[1], p->m[2], nrhs), 256);
+    *off_norms = t;
+  } else {
+    const size_t es = p->prec() == P_F32 ? 4 : 2;
+    *off_a = 0;
+    t = align_up(P * es, 256);
+    *off_b = t;
+    t += align_up(P * es, 256);
+    *off_norms = t;
+    t += align_up(2 * kMaxRhs * sizeof(unsigned long long), 256);
+  }
+  *total = t;
+}
+
+helm_status helm_workspace_size(const helm_plan* p, int nrhs, size_t* bytes) {
+  if (!p || !bytes || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
+  size_t a, b, c;
+  workspace_layout(p, nrhs, bytes, &a, &b, &c);
+  return HELM_OK;
+}
+
+helm_status helm_get_eigen(const helm_plan* p, int axis, int* n, double* lam, double* E, double* Einv) {
+  if (!p || axis < 0 || axis > 2) return HELM_EINVAL;
+  const Axis1D& h = p->ax[axis]->host;
+  if (n) *n = h.m;
+  if (lam) std::copy(h.lam.begin(), h.lam.end(), lam);
+  if (E) std::copy(h.E.begin(), h.E.end(), E);
+  if (Einv) std::copy(h.Einv.begin(), h.Einv.end(), Einv);
+  return HELM_OK;
+}
+
+void helm_destroy(helm_plan* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Six mode products of one TPF application in precision pr, from `in` (type pr) to the
+// final x-inverse output.  bufs: two scratch buffers of type pr; the final product writes
+// `out` with epilogue epi_last (STORE in pr, or ACCUM into FP64 u).
+hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, void* b2, void* out, Epi epi_last,
+                        int nrhs, const double* sig, unsigned long long* norms, int accum_zero, hipStream_t st) {
+  const DevAxis& X = *p->ax[0];
+  const DevAxis& Y = *p->ax[1];
+  const DevAxis& Z = *p->ax[2];
+  const long long nx = p->m[0], ny = p->m[1], nz = p->m[2];
+  EpiArgs ep;
+  ep.lamx = X.lam;
+  ep.lamy = Y.lam;
+  ep.lamz = Z.lam;
+  ep.nx = static_cast<int>(nx);
+  ep.eq28 = p->opts.null_mode == HELM_NULL_PAPER_EQ28;
+  ep.norms = norms;
+  ep.rows_per_rhs = ny * nz;
+  ep.accum_zero = accum_zero;
+  for (int r = 0; r < nrhs; ++r) ep.sigma[r] = sig[r];
+  const int ip = static_cast<int>(pr);
+  hipError_t e;
+  // forward: E_x^{-1}, E_y^{-1}, E_z^{-1} + divide
+  if ((e = mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, ep, st)) != hipSuccess) return e;
+  if ((e = mode_left(pr, Y.sw[ip][0], ny, b1, pr, b2, pr, nrhs * nz, nx, EPI_STORE, ep, st)) != hipSuccess) return e;
+  if ((e = mode_left(pr, Z.sw[ip][0], nz, b2, pr, b1, pr, nrhs, nx * ny, EPI_DIVIDE, ep, st)) != hipSuccess) return e;
+  // inverse: E_z, E_y, E_x
+  if ((e = mode_left(pr, Z.sw[ip][1], nz, b1, pr, b2, pr, nrhs, nx * ny, EPI_STORE, ep, st)) != hipSuccess) return e;
+  if ((e = mode_left(pr, Y.sw[ip][1], ny, b2, pr, b1, pr, nrhs * nz, nx, EPI_STORE, ep, st)) != hipSuccess) return e;
+  const Prec tout = epi_last == EPI_ACCUM ? P_F64 : pr;
+  return mode_right(pr, X.sw[ip][1], nx, b1, pr, out, tout, nrhs * ny * nz, epi_last, ep, st);
+}
+
+StencilArgs stencil_args(const helm_plan* p, int nrhs, const double* sig) {
+  StencilArgs a;
+  a.cx = p->ax[0]->coef;
+  a.cy = p->ax[1]->coef;
+  a.cz = p->ax[2]->coef;
+  a.nx = p->m[0];
+  a.ny = p->m[1];
+  a.nz = p->m[2];
+  a.nrhs = nrhs;
+  for (int r = 0; r < nrhs; ++r) a.sigma[r] = sig[r];
+  return a;
+}
+
+}  // namespace
+
+extern "C" helm_status helm_apply(const helm_plan* p, const double* u, double* Hu, int nrhs,
+                                  const double* sigma_per_rhs, void* stream) {
+  if (!p || !u || !Hu || nrhs < 1 || nrhs > kMaxRhs || u == Hu) return HELM_EINVAL;
+  double sig[kMaxRhs];
+  for (int r = 0; r < nrhs; ++r) {
+    sig[r] = sigma_per_rhs ? sigma_per_rhs[r] : p->sigma;
+    if (!std::isfinite(sig[r])) return HELM_EINVAL;
+  }
+  DeviceGuard dg(p->device);
+  const StencilArgs a = stencil_args(p, nrhs, sig);
+  return from_hip(stencil(0, u, nullptr, Hu, P_F64, a, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int nrhs, const double* sigma_per_rhs,
+                                  void* ws, void* stream, helm_info* info) {
+  if (!p || !f || !u || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
+  if (p->refined() && f == u) return HELM_EINVAL;
+  size_t total, off_a, off_b, off_n;
+  workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n);
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0) return HELM_EINVAL;
+  double sig[kMaxRhs];
+  for (int r = 0; r < nrhs; ++r) {
+    sig[r] = sigma_per_rhs ? sigma_per_rhs[r] : p->sigma;
+    if (!std::isfinite(sig[r])) return HELM_EINVAL;
+    if (sig[r] != p->sigma && has_zero_denominator(p, sig[r])) return HELM_ESINGULAR;
+  }
+  DeviceGuard dg(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const Prec pr = p->prec();
+  if (info) {
+    info->sweeps = 1;
+    info->last_correction = 0.0;
+    info->converged = 1;
+    info->iterations = 0;
+    info->residual = 0.0;
+  }
+  hipError_t e = hipSuccess;
+  if (pr == P_F64) {
+    double* W = reinterpret_cast<double*>(w + off_a);
+    const DevAxis& X = *p->ax[0];
+    const DevAxis& Y = *p->ax[1];
+    const DevAxis& Z = *p->ax[2];
+    const long long nx = p->m[0], ny = p->m[1], nz = p->m[2];
+    if (p->opts.method == HELM_TPF) {
+      // f -> W -> u -> W -> u -> W -> u (u may alias f: f is consumed by the first product)
+      EpiArgs ep;
+      ep.lamx = X.lam;
+      ep.lamy = Y.lam;
+      ep.lamz = Z.lam;
+      ep.nx = static_cast<int>(nx);
+      ep.eq28 = p->opts.null_mode == HELM_NULL_PAPER_EQ28;
+      for (int r = 0; r < nrhs; ++r) ep.sigma[r] = sig[r];
+      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][0], nx, f, P_F64, W, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][0], ny, W, P_F64, u, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = mode_left(P_F64, Z.sw[0][0], nz, u, P_F64, W, P_F64, nrhs, nx * ny, EPI_DIVIDE, ep, st);
+      if (e == hipSuccess) e = mode_left(P_F64, Z.sw[0][1], nz, W, P_F64, u, P_F64, nrhs, nx * ny, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][1], ny, u, P_F64, W, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][1], nx, W, P_F64, u, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+    } else {
+      EpiArgs ep;
+      ep.nx = static_cast<int>(nx);
+      ThomasArgs ta;
+      ta.kdiag = Z.kdiag;
+      ta.koff = Z.koff;
+      ta.vol = Z.vol;
+      ta.lamx = X.lam;
+      ta.lamy = Y.lam;
+      ta.nx = static_cast<int>(nx);
+      ta.ny = static_cast<int>(ny);
+      ta.nz = static_cast<int>(nz);
+      ta.nrhs = nrhs;
+      bool null_line = false;
+      for (int r = 0; r < nrhs; ++r) {
+        ta.sigma[r] = sig[r];
+        null_line = null_line || (p->all_neumann && sig[r] == 0.0);
+      }
+      // The singular (0,0) line exists only for RHS with sigma = 0 on an all-Neumann plan;
+      // when every RHS has it, Thomas skips the line and the eigen path solves it.
+      bool all_null = true;
+      for (int r = 0; r < nrhs; ++r) all_null = all_null && p->all_neumann && sig[r] == 0.0;
+      if (null_line && !all_null) return HELM_EINVAL;  // mixed shifts on a singular plan: not supported
+      ta.skip_null = all_null ? 1 : 0;
+      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][0], nx, f, P_F64, W, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][0], ny, W, P_F64, u, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = thomas_z(u, ta, w + off_b, st);
+      if (e == hipSuccess && all_null)
+        e = null_line_z(u, Z.E, Z.Einv, Z.lam, ta.nx, ta.ny, ta.nz, nrhs,
+                        p->opts.null_mode == HELM_NULL_PAPER_EQ28, st);
+      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][1], ny, u, P_F64, W, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
+      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][1], nx, W, P_F64, u, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+    }
+    return from_hip(e);
+  }
+
+  // Low-precision products, optionally refined.
+  void* L1 = w + off_a;
+  void* L2 = w + off_b;
+  unsigned long long* norms = reinterpret_cast<unsigned long long*>(w + off_n);
+  const StencilArgs sa = stencil_args(p, nrhs, sig);
+  // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.
+  if (e == hipSuccess) e = zero_u64(norms, 2 * nrhs, st);
+  if (e == hipSuccess) e = stencil(2, nullptr, f, L1, pr, sa, st);
+  if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st);
+  if (e != hipSuccess) return from_hip(e);
+  if (!p->refined()) return HELM_OK;
+  std::lock_guard<std::mutex> lk(p->mu);
+  int sweeps = 1;
+  double last = 0.0;
+  bool conv = false;
+  while (sweeps < p->opts.max_sweeps) {
+    if (e == hipSuccess) e = zero_u64(norms, 2 * nrhs, st);
+    if (e == hipSuccess) e = stencil(1, u, f, L1, pr, sa, st);
+    if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->host_norms, norms, 2 * nrhs * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return from_hip(e);
+    ++sweeps;
+    last = 0.0;
+    bool finite = true;
+    for (int r = 0; r < nrhs; ++r) {
+      double dm, um;
+      std::memcpy(&dm, &p->host_norms[2 * r], 8);
+      std::memcpy(&um, &p->host_norms[2 * r + 1], 8);
+      if (!std::isfinite(dm) || !std::isfinite(um)) finite = false;
+      const double rel = um > 0.0 ? dm / um : (dm > 0.0 ? INFINITY : 0.0);
+      last = std::max(last, rel);
+    }
+    if (!finite) {
+      if (info) {
+        info->sweeps = sweeps;
+        info->last_correction = last;
+        info->converged = 0;
+      }
+      return HELM_ENONFINITE;
+    }
+    if (last <= p->opts.ir_tol) {
+      conv = true;
+      break;
+    }
+  }
+  if (info) {
+    info->sweeps = sweeps;
+    info->last_correction = last;
+    info->converged = conv ? 1 : 0;
+  }
+  return conv ? HELM_OK : HELM_ENOTCONVERGED;
+}
+
+extern "C" helm_status helm_pressure_setup(const helm_grid* grid, const helm_opts* opts, helm_plan** out) {
+  if (!grid) return HELM_EINVAL;
+  helm_grid g = *grid;
+  for (int d = 0; d < 3; ++d) g.loc[d] = HELM_CELL;
+  helm_bc bc;
+  for (int d = 0; d < 3; ++d) bc.lo[d] = bc.hi[d] = HELM_NEUMANN;
+  return helm_setup(&g, &bc, 0.0, opts, out);
+}
+
+extern "C" helm_status helm_pressure_solve(helm_plan* p, const double* f, double* pr, int nrhs, void* ws, void* stream,
+                                           helm_info* info) {
+  if (!p || !p->all_neumann || p->sigma != 0.0) return HELM_EINVAL;
+  return helm_solve(p, f, pr, nrhs, nullptr, ws, stream, info);
+}
