@@ -61,12 +61,16 @@ def solve_neumann_bordered(K3, vol, f):
     return x[:N]
 
 
-def solve_pcg(K3, vol, sigma, f, tol=1e-14, maxit=100000, neumann=False, x0=None, verbose=False):
+def solve_pcg(K3, vol, sigma, f, tol=1e-14, maxit=100000, neumann=False, x0=None, verbose=False,
+              max_restarts=4):
     """Jacobi-preconditioned CG on (K3 + sigma Vol) u = Vol f.
 
-    Stops when the recursively updated residual drops below tol * ||b||, then
-    recomputes the true residual.  Returns (u, info) with info holding the
-    iteration count, the true relative residual and the wall time.
+    Runs CG until the recursively updated residual drops below tol * ||b||, then
+    recomputes the true residual b - S x; while that is still above tol * ||b||, CG is
+    restarted from the current iterate (residual replacement, at most max_restarts
+    times), because in floating point the recursive residual keeps shrinking after the
+    true one has stalled.  Returns (u, info) with the total iteration count, the true
+    relative residual, the number of restarts and the wall time.
     """
     t0 = time.perf_counter()
     S = (K3 + sp.diags(sigma * vol)).tocsr()
@@ -75,30 +79,40 @@ def solve_pcg(K3, vol, sigma, f, tol=1e-14, maxit=100000, neumann=False, x0=None
     b = vol * f
     dinv = 1.0 / S.diagonal()
     x = np.zeros_like(b) if x0 is None else x0.copy()
-    r = b - S @ x
-    z = dinv * r
-    p = z.copy()
-    rz = r @ z
     bn = np.linalg.norm(b)
     it = 0
-    while it < maxit:
-        if np.linalg.norm(r) <= tol * bn:
+    restarts = 0
+    while True:
+        r = b - S @ x
+        if neumann:
+            r -= r.sum() / r.size      # keep the residual in the range (constant null vector)
+        if np.linalg.norm(r) <= tol * bn or it >= maxit:
             break
-        q = S @ p
-        alpha = rz / (p @ q)
-        x += alpha * p
-        r -= alpha * q
+        if restarts > max_restarts:
+            break
         z = dinv * r
-        rz_new = r @ z
-        p = z + (rz_new / rz) * p
-        rz = rz_new
-        it += 1
-        if verbose and it % 100 == 0:
-            print(f"  pcg it {it} rel {np.linalg.norm(r) / bn:.3e}", flush=True)
+        p = z.copy()
+        rz = r @ z
+        while it < maxit:
+            if np.linalg.norm(r) <= tol * bn:
+                break
+            q = S @ p
+            alpha = rz / (p @ q)
+            x += alpha * p
+            r -= alpha * q
+            z = dinv * r
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+            it += 1
+            if verbose and it % 100 == 0:
+                print(f"  pcg it {it} rel {np.linalg.norm(r) / bn:.3e}", flush=True)
+        restarts += 1
     if neumann:
         x = project(x, vol)
     true_rel = np.linalg.norm(b - S @ x) / bn
-    info = dict(iterations=it, true_rel_residual=float(true_rel), seconds=time.perf_counter() - t0)
+    info = dict(iterations=it, true_rel_residual=float(true_rel), restarts=restarts - 1,
+                seconds=time.perf_counter() - t0)
     return x, info
 
 
