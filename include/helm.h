@@ -73,7 +73,10 @@ typedef struct {
 typedef struct {
   int precision;            /* HELM_FP64 (default) ... HELM_BF16_IR */
   int method;               /* HELM_TPF (default) or HELM_TPT_Z */
-  double ir_tol;            /* refinement stops when max|du| <= ir_tol * max|u| (default 1e-11) */
+  double ir_tol;            /* refinement stops when the correction max|du| / max|u| of a sweep, or
+                               its product with the observed contraction factor (the predicted
+                               next correction, when that factor is below 1/2), is <= ir_tol
+                               (default 1e-11) */
   int max_sweeps;           /* refinement sweep limit, including the first solve (default 12) */
   int null_mode;            /* HELM_NULL_PROJECT (default) or HELM_NULL_PAPER_EQ28 */
 } helm_opts;
@@ -157,16 +160,33 @@ helm_status helm_pmatrix_workspace_size(const helm_pmat* pm, int restart, size_t
 /* y = C p (one right-hand side), device pointers over the pressure grid. */
 helm_status helm_pmatrix_apply(helm_pmat* pm, const double* p, double* y, void* ws, void* stream);
 
-/* Solves C p = b by right-preconditioned flexible GMRES(restart) with the pressure
- * Laplacian as preconditioner (the Krylov inverse of C in Section 2).  b must have zero
- * volume-weighted mean; p is returned with zero volume-weighted mean.  Stops when the
- * relative residual ||b - C p|| / ||b|| <= tol or after max_it iterations (ENOTCONVERGED).
- * use_precond = 0 runs plain GMRES (for comparison).  Synchronizes once per iteration. */
+/* Solves C p = b by right-preconditioned flexible GMRES(restart) (the Krylov inverse of C
+ * in Section 2).  use_precond: 0 = none; 1 = the inverse pressure Laplacian (the paper's
+ * preconditioner, exact in the Chorin limit tau -> 0); 2 = I + (1/tau) A_p^{-1}, where A_p is
+ * the pressure Laplacian (Cahouet & Chabard's form: it equals option 1 as tau -> 0 and the
+ * identity as tau -> infinity).  b must have zero volume-weighted mean; p is returned with
+ * zero volume-weighted mean.  Stops when the relative residual ||b - C p|| / ||b|| <= tol
+ * (confirmed with a true residual) or after max_it iterations (ENOTCONVERGED).
+ * Synchronizes a few times per iteration (Gram-Schmidt coefficients). */
 helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double* p, double tol, int max_it,
                                int restart, int use_precond, void* ws, void* stream,
                                helm_info* info);
 
 void helm_pmatrix_destroy(helm_pmat* pm);
+
+/* Stage timing (a tracing aid).  When enabled on a plan, every kernel launch made by
+ * helm_solve / helm_apply with that plan is bracketed by two HIP events recorded on the
+ * call's stream, tagged with its stage below.  helm_profile_read synchronizes those events,
+ * adds the elapsed milliseconds and launch counts per stage into ms[HELM_NSTAGES] and
+ * launches[HELM_NSTAGES] (host arrays), and clears the records.  Enabling or disabling
+ * also clears them.  Not thread-safe with concurrent solves on the same plan. */
+enum {
+  HELM_STAGE_X_FWD = 0, HELM_STAGE_Y_FWD, HELM_STAGE_Z_FWD_DIV, HELM_STAGE_Z_INV, HELM_STAGE_Y_INV,
+  HELM_STAGE_X_INV, HELM_STAGE_THOMAS, HELM_STAGE_NULL_LINE, HELM_STAGE_RESIDUAL, HELM_STAGE_CONVERT,
+  HELM_STAGE_APPLY, HELM_STAGE_OTHER, HELM_NSTAGES
+};
+helm_status helm_profile_enable(helm_plan* plan, int enable);
+helm_status helm_profile_read(helm_plan* plan, double* ms, int* launches);
 
 /* Host-only helpers (no device needed), for checking the setup stage on any machine. */
 /* 1D operator of one axis: lower/diag/upper rows of A = V^{-1} K (each of length m, the

@@ -115,7 +115,7 @@ class Plan:
         p = ws.data_ptr()
         return C.c_void_p((p + 255) // 256 * 256)
 
-    def solve(self, f, out=None, sigma=None, stream=None, workspace=None):
+    def solve(self, f, out=None, sigma=None, stream=None, workspace=None, allow_unconverged=False):
         """u = H^{-1} f for f: float64 CUDA tensor [nrhs, nz, ny, nx] (or [nz, ny, nx])."""
         torch = _torch()
         squeeze = f.dim() == 3
@@ -141,7 +141,8 @@ class Plan:
                     _stream_ptr(stream), C.byref(info))
         self.last_info = dict(sweeps=info.sweeps, last_correction=info.last_correction,
                               converged=bool(info.converged))
-        check(st, "helm_solve")
+        if not (allow_unconverged and st == _lib.HELM_ENOTCONVERGED):
+            check(st, "helm_solve")
         return u[0] if squeeze else u
 
     def apply(self, u, sigma=None, stream=None):
@@ -159,6 +160,17 @@ class Plan:
         check(load().helm_apply(self._h, C.c_void_p(u4.data_ptr()), C.c_void_p(out.data_ptr()), nrhs, sig,
                                 _stream_ptr(stream)), "helm_apply")
         return out[0] if u.dim() == 3 else out
+
+    def profile(self, enable=True):
+        """Enable/disable per-launch stage timing (helm_profile_enable)."""
+        check(load().helm_profile_enable(self._h, int(bool(enable))), "helm_profile_enable")
+
+    def profile_read(self):
+        """{stage: (milliseconds, launches)} accumulated since the last read (helm_profile_read)."""
+        ms = (C.c_double * len(_lib.STAGES))()
+        n = (C.c_int * len(_lib.STAGES))()
+        check(load().helm_profile_read(self._h, ms, n), "helm_profile_read")
+        return {name: (ms[i], n[i]) for i, name in enumerate(_lib.STAGES) if n[i]}
 
     def eigen(self, axis):
         lib = load()
@@ -241,12 +253,13 @@ class PressureMatrix:
                                         self._workspace(30, p.device), _stream_ptr(stream)), "helm_pmatrix_apply")
         return y
 
-    def solve(self, b, tol=1e-10, max_it=500, restart=30, precondition=True, stream=None):
+    def solve(self, b, tol=1e-10, max_it=500, restart=30, precondition=2, stream=None):
+        """p with C p = b by FGMRES; precondition: 0 none, 1 pressure Laplacian, 2 I + (1/tau) A_p^{-1}."""
         torch = _torch()
         p = torch.empty_like(b)
         info = _lib.HelmInfo()
         st = load().helm_pmatrix_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(p.data_ptr()), float(tol),
-                                       int(max_it), int(restart), int(bool(precondition)),
+                                       int(max_it), int(restart), int(precondition),
                                        self._workspace(restart, b.device), _stream_ptr(stream), C.byref(info))
         self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK)
         if st not in (_lib.HELM_OK, _lib.HELM_ENOTCONVERGED):

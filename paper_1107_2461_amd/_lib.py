@@ -13,6 +13,8 @@ CELL, FACE = 0, 1
 FP64, FP32, BF16, FP32_IR, BF16_IR = range(5)
 TPF, TPT_Z = 0, 1
 NULL_PROJECT, NULL_PAPER_EQ28 = 0, 1
+STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv", "thomas", "null_line", "residual", "convert",
+          "apply", "other")
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp32_ir": FP32_IR, "bf16_ir": BF16_IR}
 METHODS = {"tpf": TPF, "tpt": TPT_Z}
@@ -59,6 +61,8 @@ SIGNATURES = {
     "helm_pmatrix_solve": (C.c_int, [P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P,
                                      C.POINTER(HelmInfo)]),
     "helm_pmatrix_destroy": (None, [P]),
+    "helm_profile_enable": (C.c_int, [P, C.c_int]),
+    "helm_profile_read": (C.c_int, [P, DP, IP]),
     "helm_host_operator_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
     "helm_host_eigen_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP]),
 }

@@ -3,6 +3,7 @@
 // solve of the TPT variant, the FP64 7-point operator/residual and small helpers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 
@@ -213,47 +214,78 @@ hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const d
 }
 
 // ------------------------------------------------------------------ 7-point operator / residual
+// A block of 64 x 4 lanes owns a 64 x 4 patch of (x, y) lines and marches along z through a
+// chunk of planes, carrying u(k-1), u(k), u(k+1) in registers, so u and f stream through
+// once; x and y neighbours come from the lanes next door (L1) or the adjacent patch (L2).
 template <typename TOut>
-__global__ __launch_bounds__(256) void k_stencil(int mode, const double* __restrict__ u, const double* __restrict__ f,
-                                                 TOut* __restrict__ out, StencilArgs a) {
-  const long long P = static_cast<long long>(a.nx) * a.ny * a.nz;
-  const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= P * a.nrhs) return;
-  if (mode == 2) {  // plain conversion of f (the residual of u = 0)
-    out[idx] = store_cvt<TOut>(f[idx]);
-    return;
+__global__ __launch_bounds__(256) void k_stencil(int mode, const double* __restrict__ u,
+                                                 const double* __restrict__ f, TOut* __restrict__ out,
+                                                 StencilArgs a, int zchunk, int nzc) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int zc = blockIdx.z % nzc;
+  const int r = blockIdx.z / nzc;
+  if (i >= a.nx || j >= a.ny) return;
+  const int k0 = zc * zchunk;
+  const int k1 = min(a.nz, k0 + zchunk);
+  if (k0 >= k1) return;
+  const long long plane = static_cast<long long>(a.nx) * a.ny;
+  const long long off = static_cast<long long>(r) * plane * a.nz + static_cast<long long>(j) * a.nx + i;
+  const double* ur = u + off;
+  const double cxl = a.cx[3 * i], cxd = a.cx[3 * i + 1], cxu = a.cx[3 * i + 2];
+  const double cyl = a.cy[3 * j], cyd = a.cy[3 * j + 1], cyu = a.cy[3 * j + 2];
+  const double diag_xy = a.sigma[r] + cxd + cyd;
+  const bool hx_lo = i > 0, hx_hi = i + 1 < a.nx, hy_lo = j > 0, hy_hi = j + 1 < a.ny;
+  double u_dn = k0 > 0 ? ur[(k0 - 1) * plane] : 0.0;
+  double u_c = ur[k0 * plane];
+  for (int k = k0; k < k1; ++k) {
+    const long long q = k * plane;
+    const double u_up = (k + 1 < a.nz) ? ur[q + plane] : 0.0;
+    double h = (diag_xy + a.cz[3 * k + 1]) * u_c + a.cz[3 * k] * u_dn + a.cz[3 * k + 2] * u_up;
+    if (hx_lo) h += cxl * ur[q - 1];
+    if (hx_hi) h += cxu * ur[q + 1];
+    if (hy_lo) h += cyl * ur[q - a.nx];
+    if (hy_hi) h += cyu * ur[q + a.nx];
+    const double res = mode == 1 ? f[off + q] - h : h;
+    out[off + q] = store_cvt<TOut>(res);
+    u_dn = u_c;
+    u_c = u_up;
   }
-  long long t = idx;
-  const int i = static_cast<int>(t % a.nx);
-  t /= a.nx;
-  const int j = static_cast<int>(t % a.ny);
-  t /= a.ny;
-  const int k = static_cast<int>(t % a.nz);
-  const int r = static_cast<int>(t / a.nz);
-  const long long sy = a.nx, sz = static_cast<long long>(a.nx) * a.ny;
-  const double uc = u[idx];
-  double h = (a.sigma[r] + a.cx[3 * i + 1] + a.cy[3 * j + 1] + a.cz[3 * k + 1]) * uc;
-  if (i > 0) h += a.cx[3 * i] * u[idx - 1];
-  if (i + 1 < a.nx) h += a.cx[3 * i + 2] * u[idx + 1];
-  if (j > 0) h += a.cy[3 * j] * u[idx - sy];
-  if (j + 1 < a.ny) h += a.cy[3 * j + 2] * u[idx + sy];
-  if (k > 0) h += a.cz[3 * k] * u[idx - sz];
-  if (k + 1 < a.nz) h += a.cz[3 * k + 2] * u[idx + sz];
-  const double res = mode == 1 ? f[idx] - h : h;
-  out[idx] = store_cvt<TOut>(res);
+}
+
+template <typename TOut>
+__global__ __launch_bounds__(256) void k_convert(const double* __restrict__ f, TOut* __restrict__ out, long long n) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = store_cvt<TOut>(f[i]);
 }
 
 hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout, const StencilArgs& a,
                    hipStream_t st) {
   const long long n = static_cast<long long>(a.nx) * a.ny * a.nz * a.nrhs;
   if (n == 0) return hipSuccess;
-  const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
+  if (mode == 2) {
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
+    if (tout == P_F64)
+      hipLaunchKernelGGL(k_convert<double>, grid, block, 0, st, f, static_cast<double*>(out), n);
+    else if (tout == P_F32)
+      hipLaunchKernelGGL(k_convert<float>, grid, block, 0, st, f, static_cast<float*>(out), n);
+    else
+      hipLaunchKernelGGL(k_convert<bf16_t>, grid, block, 0, st, f, static_cast<bf16_t*>(out), n);
+    return hipGetLastError();
+  }
+  const int bx = (a.nx + 63) / 64, by = (a.ny + 3) / 4;
+  const long long xy_blocks = static_cast<long long>(bx) * by * a.nrhs;
+  int nzc = static_cast<int>(std::max<long long>(1, std::min<long long>(a.nz, (2048 + xy_blocks - 1) / xy_blocks)));
+  const int zchunk = (a.nz + nzc - 1) / nzc;
+  nzc = (a.nz + zchunk - 1) / zchunk;
+  const dim3 grid(bx, by, nzc * a.nrhs), block(64, 4);
   if (tout == P_F64)
-    hipLaunchKernelGGL(k_stencil<double>, grid, block, 0, st, mode, u, f, static_cast<double*>(out), a);
+    hipLaunchKernelGGL(k_stencil<double>, grid, block, 0, st, mode, u, f, static_cast<double*>(out), a, zchunk, nzc);
   else if (tout == P_F32)
-    hipLaunchKernelGGL(k_stencil<float>, grid, block, 0, st, mode, u, f, static_cast<float*>(out), a);
+    hipLaunchKernelGGL(k_stencil<float>, grid, block, 0, st, mode, u, f, static_cast<float*>(out), a, zchunk, nzc);
   else
-    hipLaunchKernelGGL(k_stencil<bf16_t>, grid, block, 0, st, mode, u, f, static_cast<bf16_t*>(out), a);
+    hipLaunchKernelGGL(k_stencil<bf16_t>, grid, block, 0, st, mode, u, f, static_cast<bf16_t*>(out), a, zchunk,
+                       nzc);
   return hipGetLastError();
 }
 
@@ -303,14 +335,16 @@ __global__ void k_wsum_final(double* part, int blocks_per_rhs, double inv_volsum
     mean[r] = s * inv_volsum;
   }
 }
-__global__ __launch_bounds__(256) void k_sub_mean(double* x, const double* mean, long long P, int nrhs) {
+__global__ __launch_bounds__(256) void k_sub_mean(double* x, const double* mean, long long P,
+                                                  unsigned long long mask) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= P * nrhs) return;
-  x[i] -= mean[i / P];
+  const int r = blockIdx.y;
+  if (i >= P || !((mask >> r) & 1ull)) return;
+  x[r * P + i] -= mean[r];
 }
 
 hipError_t remove_mean(double* x, const double* volx, const double* voly, const double* volz, int nx, int ny, int nz,
-                       int nrhs, double inv_volsum, double* scratch, hipStream_t st) {
+                       int nrhs, double inv_volsum, unsigned long long mask, double* scratch, hipStream_t st) {
   // scratch: at least nrhs * (kMeanBlocks + 1) doubles
   double* part = scratch;
   double* mean = scratch + static_cast<long long>(nrhs) * kMeanBlocks;
@@ -318,8 +352,145 @@ hipError_t remove_mean(double* x, const double* volx, const double* voly, const 
                      kMeanBlocks, part);
   hipLaunchKernelGGL(k_wsum_final, dim3(nrhs), dim3(64), 0, st, part, kMeanBlocks, inv_volsum, mean);
   const long long P = static_cast<long long>(nx) * ny * nz;
-  hipLaunchKernelGGL(k_sub_mean, dim3(static_cast<unsigned>((P * nrhs + 255) / 256)), dim3(256), 0, st, x, mean, P,
-                     nrhs);
+  hipLaunchKernelGGL(k_sub_mean, dim3(static_cast<unsigned>((P + 255) / 256), nrhs), dim3(256), 0, st, x, mean, P,
+                     mask);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MAC grad / div (pressure matrix)
+// 3D launch over (x, y, z) of the output grid: no index division.
+__global__ __launch_bounds__(256) void k_mac_grad(int d, const double* __restrict__ p, double* __restrict__ v, int nx,
+                                                  int ny, int nz, const double* __restrict__ inv_dc) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  int vx = nx, vy = ny;
+  if (d == 0) vx = nx - 1;
+  if (d == 1) vy = ny - 1;
+  const int vz = d == 2 ? nz - 1 : nz;
+  if (i >= vx || j >= vy || k >= vz) return;
+  const long long pidx = (static_cast<long long>(k) * ny + j) * nx + i;
+  const long long step = d == 0 ? 1 : (d == 1 ? nx : static_cast<long long>(nx) * ny);
+  const int c = d == 0 ? i : (d == 1 ? j : k);
+  v[(static_cast<long long>(k) * vy + j) * vx + i] = (p[pidx + step] - p[pidx]) * inv_dc[c];
+}
+
+__global__ __launch_bounds__(256) void k_mac_div_acc(int d, const double* __restrict__ v, double* __restrict__ y,
+                                                     int nx, int ny, int nz, const double* __restrict__ inv_w,
+                                                     double alpha) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= nx || j >= ny || k >= nz) return;
+  int vx = nx, vy = ny;
+  if (d == 0) vx = nx - 1;
+  if (d == 1) vy = ny - 1;
+  const int c = d == 0 ? i : (d == 1 ? j : k);
+  const int nd = d == 0 ? nx : (d == 1 ? ny : nz);
+  const long long vidx = (static_cast<long long>(k) * vy + j) * vx + i;  // face above the cell (node c)
+  const long long step = d == 0 ? 1 : (d == 1 ? vx : static_cast<long long>(vx) * vy);
+  const double hi = c < nd - 1 ? v[vidx] : 0.0;
+  const double lo = c > 0 ? v[vidx - step] : 0.0;
+  y[(static_cast<long long>(k) * ny + j) * nx + i] += alpha * (hi - lo) * inv_w[c];
+}
+
+hipError_t mac_grad(int d, const double* p, double* v, const int n[3], const double* inv_dc, hipStream_t st) {
+  const int vz = d == 2 ? n[2] - 1 : n[2];
+  const dim3 grid((n[0] + 63) / 64, (n[1] + 3) / 4, vz), block(64, 4);
+  hipLaunchKernelGGL(k_mac_grad, grid, block, 0, st, d, p, v, n[0], n[1], n[2], inv_dc);
+  return hipGetLastError();
+}
+
+hipError_t mac_div_acc(int d, const double* v, double* y, const int n[3], const double* inv_w, double alpha,
+                       hipStream_t st) {
+  const dim3 grid((n[0] + 63) / 64, (n[1] + 3) / 4, n[2]), block(64, 4);
+  hipLaunchKernelGGL(k_mac_div_acc, grid, block, 0, st, d, v, y, n[0], n[1], n[2], inv_w, alpha);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* y, long long n, double value) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = value;
+}
+hipError_t fill(double* y, long long n, double value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, y, n, value);
+  return hipGetLastError();
+}
+
+// Stage 1: block b of vector j sums a strided slice of V_j . w into partial[j][b].
+__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, long long ldv,
+                                                  const double* __restrict__ w, long long n,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int j = blockIdx.y;
+  const double* vj = V + j * ldv;
+  double s = 0.0;
+  for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * 256)
+    s += vj[i] * w[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[static_cast<long long>(j) * gridDim.x + blockIdx.x] = sh[0];
+}
+// Stage 2: one block per vector sums its partials in a fixed tree order.
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int nblk,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += partial[static_cast<long long>(j) * nblk + b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sh[0];
+}
+
+hipError_t multi_dot(const double* V, long long ldv, int nvec, const double* w, long long n, double* partial,
+                     double* out, hipStream_t st) {
+  if (nvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_multidot, dim3(kDotBlocks, nvec), dim3(256), 0, st, V, ldv, w, n, partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(nvec), dim3(256), 0, st, partial, kDotBlocks, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V,
+                                                    long long ldv, int nvec, const double* __restrict__ coef,
+                                                    long long n) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = w[i];
+  for (int j = 0; j < nvec; ++j) s += coef[j] * V[j * ldv + i];
+  w[i] = s;
+}
+hipError_t multi_axpy(double* w, const double* V, long long ldv, int nvec, const double* coef, long long n,
+                      hipStream_t st) {
+  if (n <= 0 || nvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_multi_axpy, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, w, V, ldv, nvec,
+                     coef, n);
+  return hipGetLastError();
+}
+
+__global__ void k_axpby(double* y, double a, const double* x, double b, long long n) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * y[i] + b * x[i];
+}
+hipError_t axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, y, a, x, b, n);
+  return hipGetLastError();
+}
+
+__global__ void k_scale(double* y, const double* x, double a, long long n) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+hipError_t scale(double* y, const double* x, double a, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, y, x, a, n);
   return hipGetLastError();
 }
 

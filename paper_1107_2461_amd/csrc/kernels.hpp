@@ -87,8 +87,31 @@ hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st);
 // Volume-weighted mean removal per RHS: x -= sum(vol * x) * inv_volsum   (FP64, in place,
 // deterministic order).  scratch: nrhs * (kMeanBlocks + 1) doubles of device memory.
 constexpr int kMeanBlocks = 512;
+// Only the RHS r with bit r of `mask` set are changed.
 hipError_t remove_mean(double* x, const double* volx, const double* voly, const double* volz,
-                       int nx, int ny, int nz, int nrhs, double inv_volsum, double* scratch,
+                       int nx, int ny, int nz, int nrhs, double inv_volsum, unsigned long long mask,
+                       double* scratch, hipStream_t st);
+
+// ---- staggered (MAC) operators and Krylov helpers for the pressure matrix (eqs. 4, 9) ----
+// Pressure grid n = (nx, ny, nz) cells; the d-velocity grid has n[d] - 1 nodes along d.
+// v = Grad_d p:  v[.., i, ..] = (p[.., i+1, ..] - p[.., i, ..]) * inv_dc[i],  i < n[d] - 1.
+hipError_t mac_grad(int d, const double* p, double* v, const int n[3], const double* inv_dc, hipStream_t st);
+// y += alpha * Div_d v:  y[.., i, ..] += alpha * (v[.., i, ..] - v[.., i-1, ..]) * inv_w[i], wall values 0.
+hipError_t mac_div_acc(int d, const double* v, double* y, const int n[3], const double* inv_w, double alpha,
                        hipStream_t st);
+// y[i] = value
+hipError_t fill(double* y, long long n, double value, hipStream_t st);
+// out[j] = sum_i V[j * ldv + i] * w[i] for j < nvec, deterministic two-stage reduction.
+// partial: nvec * kDotBlocks doubles of device scratch; out: nvec doubles (device).
+constexpr int kDotBlocks = 256;
+hipError_t multi_dot(const double* V, long long ldv, int nvec, const double* w, long long n, double* partial,
+                     double* out, hipStream_t st);
+// w[i] += sum_j coef[j] * V[j * ldv + i]   (coef: device array of nvec values)
+hipError_t multi_axpy(double* w, const double* V, long long ldv, int nvec, const double* coef, long long n,
+                      hipStream_t st);
+// y[i] = a * y[i] + b * x[i]
+hipError_t axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st);
+// y[i] = a * x[i]   (x may equal y)
+hipError_t scale(double* y, const double* x, double a, long long n, hipStream_t st);
 
 }  // namespace helm

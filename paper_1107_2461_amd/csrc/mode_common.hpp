@@ -105,11 +105,18 @@ inline int choose_cfg(int K) {
 inline int kblock(Prec p) { return p == P_BF16 ? 32 : 16; }
 
 // ------------------------------------------------------------------ epilogue helpers
-__device__ inline double divide_by_eigs(double v, const EpiArgs& ep, int c, long long n, int r) {
-  const int ax = static_cast<int>(n % ep.nx);
-  const int by = static_cast<int>(n / ep.nx);
-  const double den = ep.lamx[ax] + ep.lamy[by] + ep.lamz[c] + ep.sigma[r];
-  if (den == 0.0) return ep.eq28 ? v : 0.0;  // exact null mode of the all-Neumann Laplacian
+// Shift of one (x, y) column of the z-forward output: lam_x(a) + lam_y(b) + sigma(r), with
+// n = b * nx + a the column inside the RHS r.
+__device__ inline double column_shift(const EpiArgs& ep, long long n, int r) {
+  const int ni = static_cast<int>(n);
+  const int by = ni / ep.nx;
+  return ep.lamx[ni - by * ep.nx] + ep.lamy[by] + ep.sigma[r];
+}
+// Pointwise divide of eqs. 26-27 with the FP64 denominator lam_z(c) + shift; the exact zero
+// denominator of the all-Neumann null mode gives 0 (projection) or v (eq. 28: Lambda := 1).
+__device__ inline double divide_by_eigs(double v, const EpiArgs& ep, int c, double shift) {
+  const double den = ep.lamz[c] + shift;
+  if (den == 0.0) return ep.eq28 ? v : 0.0;
   return v / den;
 }
 __device__ inline double wave_max(double v) {
@@ -118,6 +125,16 @@ __device__ inline double wave_max(double v) {
 }
 __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
   atomicMax(p, static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+// RHS index of row m of the x-mode matrix, given the RHS r_lo of the workgroup's first row.
+__device__ inline long long rhs_of_row(long long m, long long r_lo, long long rows_per_rhs) {
+  long long r = r_lo, b = (r_lo + 1) * rows_per_rhs;
+  while (m >= b) {
+    ++r;
+    b += rows_per_rhs;
+  }
+  return r;
 }
 
 // Per-lane running maxima of |du| and |u| for the two RHS a workgroup can straddle.
@@ -153,9 +170,10 @@ struct NormAcc {
 };
 
 // ------------------------------------------------------------------ FP64 / FP32 left form
-template <typename TC, int W, int MB, int NB, int EPI>
-__global__ __launch_bounds__(256) void k_left(const TC* __restrict__ Msw, int KB, int K, const TC* __restrict__ X,
-                                              TC* __restrict__ Y, long long S, long long Nn, EpiArgs ep) {
+template <typename TC, int W, int MB, int NB, int EPI, int MINB = 1, bool PF = true>
+__global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, int KB, int K,
+                                                    const TC* __restrict__ X, TC* __restrict__ Y, long long S,
+                                                    long long Nn, EpiArgs ep) {
   using T = Mma<TC>;
   using acc_t = typename T::acc_t;
   using vec_t = typename T::vec_t;
@@ -170,6 +188,7 @@ __global__ __launch_bounds__(256) void k_left(const TC* __restrict__ Msw, int KB
 
   long long base[NB];
   bool colok[NB];
+  [[maybe_unused]] double den_xy[NB];  // lam_x(a) + lam_y(b) + sigma(r) of this lane's columns
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const long long c = c0 + nb * 16 + l16;
@@ -177,6 +196,7 @@ __global__ __launch_bounds__(256) void k_left(const TC* __restrict__ Msw, int KB
     const long long s = colok[nb] ? c / Nn : 0;
     const long long n = colok[nb] ? c - s * Nn : 0;
     base[nb] = s * K * Nn + n;
+    if constexpr (EPI == EPI_DIVIDE) den_xy[nb] = colok[nb] ? column_shift(ep, n, static_cast<int>(s)) : 1.0;
   }
   acc_t acc[MB][NB];
 #pragma unroll
@@ -198,16 +218,20 @@ __global__ __launch_bounds__(256) void k_left(const TC* __restrict__ Msw, int KB
         b[nb][s] = (colok[nb] && k < K) ? X[base[nb] + static_cast<long long>(k) * Nn] : TC(0);
     }
   };
-  load(0, a_cur, b_cur);
+  if constexpr (PF) load(0, a_cur, b_cur);
   for (int kb = 0; kb < KB; ++kb) {
-    if (kb + 1 < KB) load(kb + 1, a_nxt, b_nxt);
+    if constexpr (PF) {
+      if (kb + 1 < KB) load(kb + 1, a_nxt, b_nxt);
+    } else {
+      load(kb, a_cur, b_cur);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = T::mma(a_cur[mb][s], b_cur[nb][s], acc[mb][nb]);
-    if (kb + 1 < KB) {
+    if (PF && kb + 1 < KB) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) a_cur[mb] = a_nxt[mb];
 #pragma unroll
@@ -226,10 +250,7 @@ __global__ __launch_bounds__(256) void k_left(const TC* __restrict__ Msw, int KB
         if (a >= K || !colok[nb]) continue;
         const long long idx = base[nb] + static_cast<long long>(a) * Nn;
         if constexpr (EPI == EPI_DIVIDE) {
-          const long long c = c0 + nb * 16 + l16;
-          const long long s = c / Nn;
-          Y[idx] = store_cvt<TC>(divide_by_eigs(static_cast<double>(acc[mb][nb][r]), ep, a, c - s * Nn,
-                                                static_cast<int>(s)));
+          Y[idx] = store_cvt<TC>(divide_by_eigs(static_cast<double>(acc[mb][nb][r]), ep, a, den_xy[nb]));
         } else {
           Y[idx] = static_cast<TC>(acc[mb][nb][r]);
         }
@@ -239,9 +260,10 @@ __global__ __launch_bounds__(256) void k_left(const TC* __restrict__ Msw, int KB
 // ------------------------------------------------------------------ FP64 / FP32 right form
 // Table entry (W, MB, NB) read with roles swapped: W waves span the K output columns with
 // NB := MB column blocks each; the 4/W other waves span rows with MB := NB row blocks each.
-template <typename TC, typename TOut, int W, int NB, int MB, int EPI, bool VEC>
-__global__ __launch_bounds__(256) void k_right(const TC* __restrict__ Msw, int KB, int K, const TC* __restrict__ X,
-                                               TOut* __restrict__ Y, long long Mrows, EpiArgs ep) {
+template <typename TC, typename TOut, int W, int NB, int MB, int EPI, bool VEC, int MINB = 1, bool PF = true>
+__global__ __launch_bounds__(256, MINB) void k_right(const TC* __restrict__ Msw, int KB, int K,
+                                                     const TC* __restrict__ X, TOut* __restrict__ Y, long long Mrows,
+                                                     EpiArgs ep) {
   using T = Mma<TC>;
   using acc_t = typename T::acc_t;
   using vec_t = typename T::vec_t;
@@ -285,16 +307,20 @@ __global__ __launch_bounds__(256) void k_right(const TC* __restrict__ Msw, int K
     for (int nb = 0; nb < NB; ++nb)
       b[nb] = *reinterpret_cast<const vec_t*>(Msw + ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 4);
   };
-  load(0, a_cur, b_cur);
+  if constexpr (PF) load(0, a_cur, b_cur);
   for (int kb = 0; kb < KB; ++kb) {
-    if (kb + 1 < KB) load(kb + 1, a_nxt, b_nxt);
+    if constexpr (PF) {
+      if (kb + 1 < KB) load(kb + 1, a_nxt, b_nxt);
+    } else {
+      load(kb, a_cur, b_cur);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = T::mma(a_cur[mb][s], b_cur[nb][s], acc[mb][nb]);
-    if (kb + 1 < KB) {
+    if (PF && kb + 1 < KB) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) a_cur[mb] = a_nxt[mb];
 #pragma unroll
@@ -318,7 +344,7 @@ __global__ __launch_bounds__(256) void k_right(const TC* __restrict__ Msw, int K
           const double du = static_cast<double>(acc[mb][nb][r]);
           const double un = (ep.accum_zero ? 0.0 : static_cast<double>(Y[idx])) + du;
           Y[idx] = store_cvt<TOut>(un);
-          na.add(ep, r_lo, m / ep.rows_per_rhs, du, un);
+          na.add(ep, r_lo, rhs_of_row(m, r_lo, ep.rows_per_rhs), du, un);
         } else {
           Y[idx] = store_cvt<TOut>(static_cast<double>(acc[mb][nb][r]));
         }
@@ -342,6 +368,7 @@ __global__ __launch_bounds__(256) void k_left_bf16(const bf16_t* __restrict__ Ms
   const int rb0 = wm * MB;
   long long base[NB];
   bool colok[NB];
+  [[maybe_unused]] double den_xy[NB];  // lam_x(a) + lam_y(b) + sigma(r) of this lane's columns
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const long long c = c0 + nb * 16 + l16;
@@ -349,6 +376,7 @@ __global__ __launch_bounds__(256) void k_left_bf16(const bf16_t* __restrict__ Ms
     const long long s = colok[nb] ? c / Nn : 0;
     const long long n = colok[nb] ? c - s * Nn : 0;
     base[nb] = s * K * Nn + n;
+    if constexpr (EPI == EPI_DIVIDE) den_xy[nb] = colok[nb] ? column_shift(ep, n, static_cast<int>(s)) : 1.0;
   }
   f4 acc[MB][NB];
 #pragma unroll
@@ -391,10 +419,7 @@ __global__ __launch_bounds__(256) void k_left_bf16(const bf16_t* __restrict__ Ms
         if (a >= K || !colok[nb]) continue;
         const long long idx = base[nb] + static_cast<long long>(a) * Nn;
         if constexpr (EPI == EPI_DIVIDE) {
-          const long long c = c0 + nb * 16 + l16;
-          const long long s = c / Nn;
-          Y[idx] = store_cvt<bf16_t>(
-              divide_by_eigs(static_cast<double>(acc[mb][nb][r]), ep, a, c - s * Nn, static_cast<int>(s)));
+          Y[idx] = store_cvt<bf16_t>(divide_by_eigs(static_cast<double>(acc[mb][nb][r]), ep, a, den_xy[nb]));
         } else {
           Y[idx] = f32_to_bf16(acc[mb][nb][r]);
         }
@@ -474,7 +499,7 @@ __global__ __launch_bounds__(256) void k_right_bf16(const bf16_t* __restrict__ M
           const double du = static_cast<double>(acc[mb][nb][r]);
           const double un = (ep.accum_zero ? 0.0 : static_cast<double>(Y[idx])) + du;
           Y[idx] = store_cvt<TOut>(un);
-          na.add(ep, r_lo, m / ep.rows_per_rhs, du, un);
+          na.add(ep, r_lo, rhs_of_row(m, r_lo, ep.rows_per_rhs), du, un);
         } else {
           Y[idx] = store_cvt<TOut>(static_cast<double>(acc[mb][nb][r]));
         }

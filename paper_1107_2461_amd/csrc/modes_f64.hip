@@ -1,4 +1,7 @@
 // Instantiation unit: f64 mode products (templates in mode_common.hpp).
+// FP64: no register prefetch, two workgroups per CU (measured fastest at 256^3: the
+// second workgroup hides the first one's load latency better than a prefetch buffer that
+// halves occupancy).
 #include "mode_common.hpp"
 
 namespace helm {
@@ -17,10 +20,10 @@ hipError_t mode_left_f64(int ci, const void* Msw, int K, const void* X, void* Y,
     TC* Yp = static_cast<TC*>(Y);
     if (epi == EPI_STORE) {
       constexpr int E = EPI_STORE;
-      hipLaunchKernelGGL((k_left<double, kCfgs[CI].W, kCfgs[CI].MB, kCfgs[CI].NB, E>), grid1d(blocks), dim3(256), 0, st, Mp, KB, K, Xp, Yp, S, Nn, ep);
+      hipLaunchKernelGGL((k_left<double, kCfgs[CI].W, kCfgs[CI].MB, kCfgs[CI].NB, E, 2, false>), grid1d(blocks), dim3(256), 0, st, Mp, KB, K, Xp, Yp, S, Nn, ep);
     } else if (epi == EPI_DIVIDE) {
       constexpr int E = EPI_DIVIDE;
-      hipLaunchKernelGGL((k_left<double, kCfgs[CI].W, kCfgs[CI].MB, kCfgs[CI].NB, E>), grid1d(blocks), dim3(256), 0, st, Mp, KB, K, Xp, Yp, S, Nn, ep);
+      hipLaunchKernelGGL((k_left<double, kCfgs[CI].W, kCfgs[CI].MB, kCfgs[CI].NB, E, 2, false>), grid1d(blocks), dim3(256), 0, st, Mp, KB, K, Xp, Yp, S, Nn, ep);
     } else {
       return hipErrorInvalidValue;
     }
@@ -42,10 +45,10 @@ hipError_t mode_right_f64(int ci, const void* Msw, int K, const void* X, void* Y
     double* Yp = static_cast<double*>(Y);
     if (epi != EPI_STORE) return hipErrorInvalidValue;
     if (vec)
-      hipLaunchKernelGGL((k_right<double, double, c.W, c.MB, c.NB, EPI_STORE, true>), grid1d(blocks), dim3(256), 0,
+      hipLaunchKernelGGL((k_right<double, double, c.W, c.MB, c.NB, EPI_STORE, true, 2, false>), grid1d(blocks), dim3(256), 0,
                          st, Mp, KB, K, Xp, Yp, Mrows, ep);
     else
-      hipLaunchKernelGGL((k_right<double, double, c.W, c.MB, c.NB, EPI_STORE, false>), grid1d(blocks), dim3(256), 0,
+      hipLaunchKernelGGL((k_right<double, double, c.W, c.MB, c.NB, EPI_STORE, false, 2, false>), grid1d(blocks), dim3(256), 0,
                          st, Mp, KB, K, Xp, Yp, Mrows, ep);
     return hipGetLastError();
   });

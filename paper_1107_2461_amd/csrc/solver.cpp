@@ -141,6 +141,33 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+// Optional per-launch event timing (helm_profile_enable / helm_profile_read).
+struct StageProfiler {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void clear() {
+    recs.clear();
+    used = 0;
+  }
+  ~StageProfiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct helm_plan {
   std::shared_ptr<DevAxis> ax[3];
   int m[3] = {0, 0, 0};   // unknowns per axis
@@ -150,6 +177,7 @@ struct helm_plan {
   int device = 0;
   unsigned long long* host_norms = nullptr;  // pinned, 2 * kMaxRhs
   std::mutex mu;                             // guards host_norms
+  mutable StageProfiler prof;
   ~helm_plan() {
     if (host_norms) (void)hipHostFree(host_norms);
   }
@@ -274,7 +302,7 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
 //   FP64:  W    nrhs*P doubles         (+ Thomas checkpoints for TPT_Z)
 //   low :  L1, L2  nrhs*P low-precision values each, norms 2*nrhs u64
 static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t* off_a, size_t* off_b,
-                             size_t* off_norms) {
+                             size_t* off_norms, size_t* off_mean = nullptr) {
   const size_t P = static_cast<size_t>(p->npts()) * nrhs;
   size_t t = 0;
   if (p->prec() == P_F64) {
@@ -292,6 +320,8 @@ static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t
     *off_norms = t;
     t += align_up(2 * kMaxRhs * sizeof(unsigned long long), 256);
   }
+  if (off_mean) *off_mean = t;
+  if (p->all_neumann) t += align_up(static_cast<size_t>(nrhs) * (kMeanBlocks + 1) * sizeof(double), 256);
   *total = t;
 }
 
@@ -337,6 +367,20 @@ struct DeviceGuard {
   }
 };
 
+template <typename F>
+hipError_t timed(const helm_plan* p, int stage, hipStream_t st, F&& launch) {
+  if (!p->prof.on) return launch();
+  hipEvent_t a = p->prof.take(), b = p->prof.take();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  if (e == hipSuccess) p->prof.recs.push_back({stage, a, b});
+  return e;
+}
+
 // Six mode products of one TPF application in precision pr, from `in` (type pr) to the
 // final x-inverse output.  bufs: two scratch buffers of type pr; the final product writes
 // `out` with epilogue epi_last (STORE in pr, or ACCUM into FP64 u).
@@ -359,14 +403,31 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   const int ip = static_cast<int>(pr);
   hipError_t e;
   // forward: E_x^{-1}, E_y^{-1}, E_z^{-1} + divide
-  if ((e = mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, ep, st)) != hipSuccess) return e;
-  if ((e = mode_left(pr, Y.sw[ip][0], ny, b1, pr, b2, pr, nrhs * nz, nx, EPI_STORE, ep, st)) != hipSuccess) return e;
-  if ((e = mode_left(pr, Z.sw[ip][0], nz, b2, pr, b1, pr, nrhs, nx * ny, EPI_DIVIDE, ep, st)) != hipSuccess) return e;
+  if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
+         return mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, ep, st);
+       })) != hipSuccess)
+    return e;
+  if ((e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
+         return mode_left(pr, Y.sw[ip][0], ny, b1, pr, b2, pr, nrhs * nz, nx, EPI_STORE, ep, st);
+       })) != hipSuccess)
+    return e;
+  if ((e = timed(p, HELM_STAGE_Z_FWD_DIV, st, [&] {
+         return mode_left(pr, Z.sw[ip][0], nz, b2, pr, b1, pr, nrhs, nx * ny, EPI_DIVIDE, ep, st);
+       })) != hipSuccess)
+    return e;
   // inverse: E_z, E_y, E_x
-  if ((e = mode_left(pr, Z.sw[ip][1], nz, b1, pr, b2, pr, nrhs, nx * ny, EPI_STORE, ep, st)) != hipSuccess) return e;
-  if ((e = mode_left(pr, Y.sw[ip][1], ny, b2, pr, b1, pr, nrhs * nz, nx, EPI_STORE, ep, st)) != hipSuccess) return e;
+  if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
+         return mode_left(pr, Z.sw[ip][1], nz, b1, pr, b2, pr, nrhs, nx * ny, EPI_STORE, ep, st);
+       })) != hipSuccess)
+    return e;
+  if ((e = timed(p, HELM_STAGE_Y_INV, st, [&] {
+         return mode_left(pr, Y.sw[ip][1], ny, b2, pr, b1, pr, nrhs * nz, nx, EPI_STORE, ep, st);
+       })) != hipSuccess)
+    return e;
   const Prec tout = epi_last == EPI_ACCUM ? P_F64 : pr;
-  return mode_right(pr, X.sw[ip][1], nx, b1, pr, out, tout, nrhs * ny * nz, epi_last, ep, st);
+  return timed(p, HELM_STAGE_X_INV, st, [&] {
+    return mode_right(pr, X.sw[ip][1], nx, b1, pr, out, tout, nrhs * ny * nz, epi_last, ep, st);
+  });
 }
 
 StencilArgs stencil_args(const helm_plan* p, int nrhs, const double* sig) {
@@ -394,15 +455,16 @@ extern "C" helm_status helm_apply(const helm_plan* p, const double* u, double* H
   }
   DeviceGuard dg(p->device);
   const StencilArgs a = stencil_args(p, nrhs, sig);
-  return from_hip(stencil(0, u, nullptr, Hu, P_F64, a, static_cast<hipStream_t>(stream)));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return from_hip(timed(p, HELM_STAGE_APPLY, st, [&] { return stencil(0, u, nullptr, Hu, P_F64, a, st); }));
 }
 
 extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int nrhs, const double* sigma_per_rhs,
                                   void* ws, void* stream, helm_info* info) {
   if (!p || !f || !u || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
   if (p->refined() && f == u) return HELM_EINVAL;
-  size_t total, off_a, off_b, off_n;
-  workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n);
+  size_t total, off_a, off_b, off_n, off_m;
+  workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n, &off_m);
   if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0) return HELM_EINVAL;
   double sig[kMaxRhs];
   for (int r = 0; r < nrhs; ++r) {
@@ -414,6 +476,26 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* w = static_cast<unsigned char*>(ws);
   const Prec pr = p->prec();
+  // All-Neumann Laplace RHS (sigma = 0, projection mode): the constant is invisible to the
+  // operator, so rounding in the transforms (and every refinement sweep) can leave a small
+  // constant in u; it is removed at the end with an FP64 volume-weighted mean.
+  unsigned long long null_mask = 0;
+  if (p->all_neumann && p->opts.null_mode == HELM_NULL_PROJECT)
+    for (int r = 0; r < nrhs; ++r)
+      if (sig[r] == 0.0) null_mask |= 1ull << r;
+  auto project_null = [&]() -> hipError_t {
+    if (!null_mask) return hipSuccess;
+    double vs = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      double t = 0.0;
+      for (double v : p->ax[d]->host.vol) t += v;
+      vs *= t;
+    }
+    return timed(p, HELM_STAGE_OTHER, st, [&] {
+      return remove_mean(u, p->ax[0]->vol, p->ax[1]->vol, p->ax[2]->vol, p->m[0], p->m[1], p->m[2], nrhs, 1.0 / vs,
+                         null_mask, reinterpret_cast<double*>(w + off_m), st);
+    });
+  };
   if (info) {
     info->sweeps = 1;
     info->last_correction = 0.0;
@@ -429,20 +511,8 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
     const DevAxis& Z = *p->ax[2];
     const long long nx = p->m[0], ny = p->m[1], nz = p->m[2];
     if (p->opts.method == HELM_TPF) {
-      // f -> W -> u -> W -> u -> W -> u (u may alias f: f is consumed by the first product)
-      EpiArgs ep;
-      ep.lamx = X.lam;
-      ep.lamy = Y.lam;
-      ep.lamz = Z.lam;
-      ep.nx = static_cast<int>(nx);
-      ep.eq28 = p->opts.null_mode == HELM_NULL_PAPER_EQ28;
-      for (int r = 0; r < nrhs; ++r) ep.sigma[r] = sig[r];
-      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][0], nx, f, P_F64, W, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][0], ny, W, P_F64, u, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = mode_left(P_F64, Z.sw[0][0], nz, u, P_F64, W, P_F64, nrhs, nx * ny, EPI_DIVIDE, ep, st);
-      if (e == hipSuccess) e = mode_left(P_F64, Z.sw[0][1], nz, W, P_F64, u, P_F64, nrhs, nx * ny, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][1], ny, u, P_F64, W, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][1], nx, W, P_F64, u, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+      // f -> W -> u -> W -> u -> W -> u  (u may alias f: f is consumed by the first product)
+      e = tpf_products(p, P_F64, f, W, u, u, EPI_STORE, nrhs, sig, nullptr, 0, st);
     } else {
       EpiArgs ep;
       ep.nx = static_cast<int>(nx);
@@ -467,15 +537,30 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
       for (int r = 0; r < nrhs; ++r) all_null = all_null && p->all_neumann && sig[r] == 0.0;
       if (null_line && !all_null) return HELM_EINVAL;  // mixed shifts on a singular plan: not supported
       ta.skip_null = all_null ? 1 : 0;
-      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][0], nx, f, P_F64, W, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][0], ny, W, P_F64, u, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = thomas_z(u, ta, w + off_b, st);
+      if (e == hipSuccess)
+        e = timed(p, HELM_STAGE_X_FWD, st, [&] {
+          return mode_right(P_F64, X.sw[0][0], nx, f, P_F64, W, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+        });
+      if (e == hipSuccess)
+        e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
+          return mode_left(P_F64, Y.sw[0][0], ny, W, P_F64, u, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
+        });
+      if (e == hipSuccess) e = timed(p, HELM_STAGE_THOMAS, st, [&] { return thomas_z(u, ta, w + off_b, st); });
       if (e == hipSuccess && all_null)
-        e = null_line_z(u, Z.E, Z.Einv, Z.lam, ta.nx, ta.ny, ta.nz, nrhs,
-                        p->opts.null_mode == HELM_NULL_PAPER_EQ28, st);
-      if (e == hipSuccess) e = mode_left(P_F64, Y.sw[0][1], ny, u, P_F64, W, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
-      if (e == hipSuccess) e = mode_right(P_F64, X.sw[0][1], nx, W, P_F64, u, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+        e = timed(p, HELM_STAGE_NULL_LINE, st, [&] {
+          return null_line_z(u, Z.E, Z.Einv, Z.lam, ta.nx, ta.ny, ta.nz, nrhs,
+                             p->opts.null_mode == HELM_NULL_PAPER_EQ28, st);
+        });
+      if (e == hipSuccess)
+        e = timed(p, HELM_STAGE_Y_INV, st, [&] {
+          return mode_left(P_F64, Y.sw[0][1], ny, u, P_F64, W, P_F64, nrhs * nz, nx, EPI_STORE, ep, st);
+        });
+      if (e == hipSuccess)
+        e = timed(p, HELM_STAGE_X_INV, st, [&] {
+          return mode_right(P_F64, X.sw[0][1], nx, W, P_F64, u, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
+        });
     }
+    if (e == hipSuccess) e = project_null();
     return from_hip(e);
   }
 
@@ -485,18 +570,18 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   unsigned long long* norms = reinterpret_cast<unsigned long long*>(w + off_n);
   const StencilArgs sa = stencil_args(p, nrhs, sig);
   // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.
-  if (e == hipSuccess) e = zero_u64(norms, 2 * nrhs, st);
-  if (e == hipSuccess) e = stencil(2, nullptr, f, L1, pr, sa, st);
+  if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs, st); });
+  if (e == hipSuccess) e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, pr, sa, st); });
   if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st);
   if (e != hipSuccess) return from_hip(e);
-  if (!p->refined()) return HELM_OK;
+  if (!p->refined()) return from_hip(project_null());
   std::lock_guard<std::mutex> lk(p->mu);
   int sweeps = 1;
-  double last = 0.0;
+  double last = 0.0, prev = 1.0;  // the first solve's "correction" is u itself
   bool conv = false;
   while (sweeps < p->opts.max_sweeps) {
-    if (e == hipSuccess) e = zero_u64(norms, 2 * nrhs, st);
-    if (e == hipSuccess) e = stencil(1, u, f, L1, pr, sa, st);
+    if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs, st); });
+    if (e == hipSuccess) e = timed(p, HELM_STAGE_RESIDUAL, st, [&] { return stencil(1, u, f, L1, pr, sa, st); });
     if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(p->host_norms, norms, 2 * nrhs * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
@@ -521,16 +606,21 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
       }
       return HELM_ENONFINITE;
     }
-    if (last <= p->opts.ir_tol) {
+    // Stop when the correction is below tolerance, or when the observed contraction
+    // rho = last / prev predicts the next correction (the remaining error) below it.
+    const double rho = last / prev;
+    if (last <= p->opts.ir_tol || (rho < 0.5 && rho * last <= p->opts.ir_tol)) {
       conv = true;
       break;
     }
+    prev = last;
   }
   if (info) {
     info->sweeps = sweeps;
     info->last_correction = last;
     info->converged = conv ? 1 : 0;
   }
+  if ((e = project_null()) != hipSuccess) return from_hip(e);
   return conv ? HELM_OK : HELM_ENOTCONVERGED;
 }
 
@@ -547,4 +637,28 @@ extern "C" helm_status helm_pressure_solve(helm_plan* p, const double* f, double
                                            helm_info* info) {
   if (!p || !p->all_neumann || p->sigma != 0.0) return HELM_EINVAL;
   return helm_solve(p, f, pr, nrhs, nullptr, ws, stream, info);
+}
+
+extern "C" helm_status helm_profile_enable(helm_plan* p, int enable) {
+  if (!p) return HELM_EINVAL;
+  p->prof.on = enable != 0;
+  p->prof.clear();
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_profile_read(helm_plan* p, double* ms, int* launches) {
+  if (!p || !ms || !launches) return HELM_EINVAL;
+  for (int i = 0; i < HELM_NSTAGES; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (const auto& r : p->prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return HELM_EDEVICE;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return HELM_EDEVICE;
+    ms[r.stage] += t;
+    launches[r.stage] += 1;
+  }
+  p->prof.clear();
+  return HELM_OK;
 }

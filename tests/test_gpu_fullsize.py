@@ -1,0 +1,134 @@
+"""Full-size GPU checks on the benchmark workloads, in the launch configuration bench.py times.
+
+The oracle cannot solve these sizes inside a test, so each comparison uses the oracle's
+solution at 2048 seeded grid points per RHS stored by tests/golden/make_oracle_samples.py
+(which calls only oracle/): err = max over samples |u - u_oracle| / max|u_oracle|.  Where a
+property holds at any size it is checked on the whole field as well (FP64 residual,
+TPF = TPT, zero mean of Neumann solutions).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fv
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1107_2461_amd import load
+    load()
+    return t
+
+
+def _golden(name):
+    path = os.path.join(GOLD, f"oracle_samples_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return json.load(open(path))
+
+
+def _sample_err(u, g):
+    u = u.reshape(len(g["rhs"]), -1)
+    errs = []
+    for r, gr in enumerate(g["rhs"]):
+        idx = np.array(gr["idx"])
+        errs.append(float(np.abs(u[r, idx] - np.array(gr["u"])).max() / gr["norminf"]))
+    return max(errs)
+
+
+def _plan(prob, **kw):
+    from paper_1107_2461_amd import Plan
+    return Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, loc=prob.loc, **kw)
+
+
+@pytest.mark.parametrize("tau", [1e-3, 1.0, 1e2])
+def test_multirhs_128_tpf_tpt_fp64(torch, tau):
+    prob, f = workloads.workload_multirhs_128(tau)
+    g = _golden(f"c2_tau{tau:g}")
+    fd = torch.from_numpy(f).cuda()
+    u_tpf = _plan(prob).solve(fd)
+    u_tpt = _plan(prob, method="tpt").solve(fd)
+    torch.cuda.synchronize()
+    a, b = u_tpf.cpu().numpy(), u_tpt.cpu().numpy()
+    e_tpf, e_tpt = _sample_err(a, g), _sample_err(b, g)
+    print(f"tau {tau}: TPF {e_tpf:.2e} TPT {e_tpt:.2e}")
+    assert e_tpf <= 1e-12 and e_tpt <= 1e-12
+    for r in range(3):   # TPF and TPT agree on the whole field (Section 5.1)
+        assert np.linalg.norm(a[r] - b[r]) / np.linalg.norm(a[r]) <= 1e-12
+
+
+def test_mixed_256_paths(torch):
+    prob, f = workloads.workload_mixed_256()
+    g = _golden("c3")
+    fd = torch.from_numpy(f).cuda()
+    out = {}
+    for precision, tol in (("fp64", 1e-12), ("fp32_ir", 1e-10), ("bf16_ir", 1e-10), ("fp32", 1e-5), ("bf16", 1e-2)):
+        plan = _plan(prob, precision=precision)
+        u = plan.solve(fd)
+        torch.cuda.synchronize()
+        err = _sample_err(u.cpu().numpy(), g)
+        out[precision] = (err, plan.last_info["sweeps"])
+        assert err <= tol, (precision, err)
+        if precision == "fp64":
+            r = (fd - plan.apply(u)).norm() / fd.norm()
+            assert float(r) <= 1e-13
+    print("256^3 errors vs oracle samples (err, sweeps):", out)
+
+
+def test_mixed_256_error_per_sweep(torch):
+    """The error against the oracle falls with every refinement sweep (BF16 and FP32)."""
+    prob, f = workloads.workload_mixed_256()
+    g = _golden("c3")
+    fd = torch.from_numpy(f).cuda()
+    for precision in ("fp32_ir", "bf16_ir"):
+        errs = []
+        for k in range(1, 9):
+            plan = _plan(prob, precision=precision, max_sweeps=k, ir_tol=1e-300)
+            u = plan.solve(fd, allow_unconverged=True)
+            torch.cuda.synchronize()
+            errs.append(_sample_err(u.cpu().numpy(), g))
+            if errs[-1] < 1e-12:
+                break
+        print(precision, "error per sweep:", ["%.2e" % e for e in errs])
+        for a, b in zip(errs, errs[1:]):
+            assert b < a or b < 1e-12
+        assert errs[-1] <= 1e-10
+
+
+def test_pressure_192x160x224_mixed(torch):
+    from paper_1107_2461_amd import Plan
+    prob, f = workloads.workload_pressure()
+    g = _golden("c4_pressure")
+    fd = torch.from_numpy(f).cuda()
+    for precision, tol in (("fp64", 1e-11), ("bf16_ir", 1e-10)):
+        plan = Plan(prob.faces, pressure=True, precision=precision)
+        u = plan.solve(fd)
+        torch.cuda.synchronize()
+        un = u.cpu().numpy()
+        err = _sample_err(un, g)
+        print(precision, "pressure err", err, plan.last_info)
+        assert err <= tol
+        _, vol = fv.assemble_3d(prob.faces, bc_lo=(1,) * 3, bc_hi=(1,) * 3)[:2]
+        assert abs((un.ravel() * vol).sum() / vol.sum()) <= 1e-12 * np.abs(un).max()
+
+
+def test_pressure_matrix_fgmres_full_size(torch):
+    from paper_1107_2461_amd import PressureMatrix
+    prob, f = workloads.workload_pressure()
+    pm = PressureMatrix(prob.faces, 1e2)
+    b = torch.from_numpy(f[0]).cuda()
+    p = pm.solve(b, tol=1e-10, max_it=200, restart=30, precondition=2)
+    info = pm.last_info
+    print("FGMRES 192x160x224 tau=100:", info)
+    assert info["converged"] and info["residual"] <= 1e-10
+    r = (b - pm.apply(p)).norm() / b.norm()
+    assert float(r) <= 1e-10
