@@ -28,8 +28,8 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 6}
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}
 RIDGE = {k: v * 1e12 / (HBM_PEAK_GBS * 1e9) for k, v in MFMA_PEAK_TFLOPS.items()}
 MODE_STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv")
 
@@ -57,10 +57,13 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
     if stage in MODE_STAGES:
         flops = 2.0 * N[stage] * npts
         es = ELEM_BYTES[prec]
+        # the last product writes the FP64 solution (the split-BF16 path writes an FP32
+        # correction instead, added by the separate update stage)
+        last = "none" if prec == "bf16x3" else "x_inv"
         s_in = 8 if (stage == "x_fwd" and prec == "fp64") else es
-        s_out = 8 if (stage == "x_inv") else es
+        s_out = 8 if stage == last else es
         byts = (s_in + s_out) * npts
-        if stage == "x_inv" and prec != "fp64":
+        if stage == last and prec != "fp64":
             byts = (es + 16) * npts          # read du (low), read + write u (FP64)
         ai = flops / byts
         if ai >= RIDGE[prec]:
@@ -72,6 +75,8 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
         byts = (8 + 8 + ELEM_BYTES[prec]) * npts     # read u, f (FP64), write r (low)
     elif stage == "convert":
         byts = (8 + ELEM_BYTES[prec]) * npts
+    elif stage == "update":
+        byts = (ELEM_BYTES[prec] + 16) * npts         # read du (FP32), read + write u (FP64)
     elif stage == "thomas":
         byts = 16 * npts                              # algorithmic: read g, write v once
     else:
@@ -82,7 +87,7 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
 
 def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     from paper_1107_2461_amd import Plan
-    prec = {"fp64": "fp64", "fp32_ir": "fp32_ir", "bf16_ir": "bf16_ir", "tpt": "fp64"}[path]
+    prec = {"fp64": "fp64", "fp32_ir": "fp32_ir", "bf16_ir": "bf16_ir", "bf16x3_ir": "bf16x3_ir", "tpt": "fp64"}[path]
     method = "tpt" if path == "tpt" else "tpf"
     plan = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, loc=prob.loc, precision=prec, method=method)
     u = torch.empty_like(f_dev)
@@ -126,7 +131,7 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     res["rel_residual"] = float(rr.max())
     N = dict(x_fwd=prob.shape_xyz[0], x_inv=prob.shape_xyz[0], y_fwd=prob.shape_xyz[1], y_inv=prob.shape_xyz[1],
              z_fwd_div=prob.shape_xyz[2], z_inv=prob.shape_xyz[2])
-    lowp = {"fp64": "fp64", "tpt": "fp64", "fp32_ir": "fp32", "bf16_ir": "bf16"}[path]
+    lowp = {"fp64": "fp64", "tpt": "fp64", "fp32_ir": "fp32", "bf16_ir": "bf16", "bf16x3_ir": "bf16x3"}[path]
     st = {}
     for name, (ms, n) in stages.items():
         rl = stage_roofline(name, ms, n, N, npts, lowp)
@@ -177,7 +182,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixed_256")
-    ap.add_argument("--paths", default="fp64,fp32_ir,bf16_ir")
+    ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

@@ -49,8 +49,13 @@ enum { HELM_DIRICHLET = 0, HELM_NEUMANN = 1 };
  * velocity component along its own direction, with wall value 0 on the wall faces). */
 enum { HELM_CELL = 0, HELM_FACE = 1 };
 /* Arithmetic of the mode products.  The *_IR forms run the products in the low precision
- * and recover FP64 accuracy by iterative refinement with an FP64 7-point residual. */
-enum { HELM_FP64 = 0, HELM_FP32 = 1, HELM_BF16 = 2, HELM_FP32_IR = 3, HELM_BF16_IR = 4 };
+ * and recover FP64 accuracy by iterative refinement with an FP64 7-point residual.
+ * BF16X3: each operand split into three bfloat16 pieces, six partial products accumulated
+ * in FP32 on the BF16 matrix cores (FP32-class accuracy at the BF16 rate), FP32 storage. */
+enum {
+  HELM_FP64 = 0, HELM_FP32 = 1, HELM_BF16 = 2, HELM_FP32_IR = 3, HELM_BF16_IR = 4,
+  HELM_BF16X3 = 5, HELM_BF16X3_IR = 6
+};
 /* TPF: eigen-transforms along x, y, z (eq. 29).  TPT_Z: eigen-transforms along x, y and
  * one Thomas tridiagonal solve per z line (end of Section 3). */
 enum { HELM_TPF = 0, HELM_TPT_Z = 1 };
@@ -71,7 +76,7 @@ typedef struct {
 } helm_bc;
 
 typedef struct {
-  int precision;            /* HELM_FP64 (default) ... HELM_BF16_IR */
+  int precision;            /* HELM_FP64 (default) ... HELM_BF16X3_IR */
   int method;               /* HELM_TPF (default) or HELM_TPT_Z */
   double ir_tol;            /* refinement stops when the correction max|du| / max|u| of a sweep, or
                                its product with the observed contraction factor (the predicted
@@ -183,7 +188,7 @@ void helm_pmatrix_destroy(helm_pmat* pm);
 enum {
   HELM_STAGE_X_FWD = 0, HELM_STAGE_Y_FWD, HELM_STAGE_Z_FWD_DIV, HELM_STAGE_Z_INV, HELM_STAGE_Y_INV,
   HELM_STAGE_X_INV, HELM_STAGE_THOMAS, HELM_STAGE_NULL_LINE, HELM_STAGE_RESIDUAL, HELM_STAGE_CONVERT,
-  HELM_STAGE_APPLY, HELM_STAGE_OTHER, HELM_NSTAGES
+  HELM_STAGE_APPLY, HELM_STAGE_OTHER, HELM_STAGE_UPDATE, HELM_NSTAGES
 };
 helm_status helm_profile_enable(helm_plan* plan, int enable);
 helm_status helm_profile_read(helm_plan* plan, double* ms, int* launches);

@@ -10,13 +10,14 @@ LIB_PATH = os.path.join(HERE, "libhelm.so")
 HELM_OK, HELM_EINVAL, HELM_ESINGULAR, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOTCONVERGED, HELM_ENONFINITE = range(7)
 DIRICHLET, NEUMANN = 0, 1
 CELL, FACE = 0, 1
-FP64, FP32, BF16, FP32_IR, BF16_IR = range(5)
+FP64, FP32, BF16, FP32_IR, BF16_IR, BF16X3, BF16X3_IR = range(7)
 TPF, TPT_Z = 0, 1
 NULL_PROJECT, NULL_PAPER_EQ28 = 0, 1
 STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv", "thomas", "null_line", "residual", "convert",
-          "apply", "other")
+          "apply", "other", "update")
 
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp32_ir": FP32_IR, "bf16_ir": BF16_IR}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp32_ir": FP32_IR, "bf16_ir": BF16_IR, "bf16x3": BF16X3,
+              "bf16x3_ir": BF16X3_IR}
 METHODS = {"tpf": TPF, "tpt": TPT_Z}
 
 

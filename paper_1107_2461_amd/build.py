@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhelm.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "modes_f64.hip", "modes_f32.hip", "modes_bf16.hip", "setup.cpp", "solver.cpp",
+SOURCES = ["kernels.hip", "modes_f64.hip", "modes_f32.hip", "modes_bf16.hip", "modes_bf16x3.hip", "setup.cpp",
+           "solver.cpp",
            "pmatrix.cpp", "server.cpp"]
 
 # Packed-FP32 instructions are disabled for all device code (they have produced silently

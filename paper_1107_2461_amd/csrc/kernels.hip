@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "mode_common.hpp"
 
@@ -56,6 +57,37 @@ void swizzle_operand(Prec p, int K, const double* M, void* out) {
           else
             static_cast<bf16_t*>(out)[o] = f32_to_bf16(static_cast<float>(v));
         }
+}
+
+hipError_t mode_rot_bf16x3(int, const void*, long long, int, const float*, void*, long long, long long, Epi, bool,
+                           const EpiArgs&, hipStream_t);
+
+size_t swizzled_bf16x3_bytes(int K) { return 3 * swizzled_bytes(P_BF16, K); }
+
+void swizzle_bf16x3(int K, const double* M, void* out) {
+  // M = M1 + M2 + M3, each piece the bfloat16 rounding of what the previous ones leave
+  const size_t n = static_cast<size_t>(K) * K;
+  std::vector<double> rem(M, M + n), piece(n);
+  const size_t stride = swizzled_bytes(P_BF16, K);
+  for (int p = 0; p < 3; ++p) {
+    for (size_t i = 0; i < n; ++i) {
+      piece[i] = static_cast<double>(bf16_to_f32(f32_to_bf16(static_cast<float>(rem[i]))));
+      rem[i] -= piece[i];
+    }
+    swizzle_operand(P_BF16, K, piece.data(), static_cast<unsigned char*>(out) + p * stride);
+  }
+}
+
+hipError_t mode_rot(const void* Msw, int K, const float* X, void* Y, long long R, long long PQ, Epi epi,
+                    const EpiArgs& ep, hipStream_t st) {
+  const int ci = choose_cfg(K);
+  if (ci < 0 || K < 1 || R < 1 || PQ < 1 || R > kMaxRhs) return hipErrorInvalidValue;
+  if ((R * PQ + 15) / 16 > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (epi == EPI_ACCUM && (ep.norms == nullptr)) return hipErrorInvalidValue;
+  const bool vec = (K % 8 == 0) && (PQ % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 32 == 0) &&
+                   (reinterpret_cast<uintptr_t>(Y) % 32 == 0);
+  const long long piece = static_cast<long long>(swizzled_bytes(P_BF16, K) / 2);
+  return mode_rot_bf16x3(ci, Msw, piece, K, X, Y, R, PQ, epi, vec, ep, st);
 }
 
 hipError_t mode_left(Prec p, const void* Msw, int K, const void* X, Prec tin, void* Y, Prec tout, long long S,
@@ -286,6 +318,82 @@ hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec t
   else
     hipLaunchKernelGGL(k_stencil<bf16_t>, grid, block, 0, st, mode, u, f, static_cast<bf16_t*>(out), a, zchunk,
                        nzc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ refinement update
+// Grid-stride over the points of one RHS (blockIdx.y); each lane updates 4 consecutive points
+// per step (16-byte FP32 load, two 16-byte FP64 load/stores).  Norms: wave max, then a block
+// max through LDS, then one striped atomic pair per workgroup.
+__global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const float* __restrict__ d, long long P,
+                                                int assign, unsigned long long* __restrict__ norms) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  __shared__ double sh[2][4];
+  __shared__ int shbad[4];
+  const int r = blockIdx.y;
+  double* ur = u + r * P;
+  const float* dr = d + r * P;
+  double dm = 0.0, um = 0.0;
+  bool bad = false;
+  const long long stride = static_cast<long long>(gridDim.x) * 1024;
+  for (long long i0 = (static_cast<long long>(blockIdx.x) * 256 + threadIdx.x) * 4; i0 < P; i0 += stride) {
+    if (i0 + 3 < P && (P & 3) == 0) {
+      const f4 dv = *reinterpret_cast<const f4*>(dr + i0);
+      d2v a = assign ? d2v{0, 0} : *reinterpret_cast<const d2v*>(ur + i0);
+      d2v b = assign ? d2v{0, 0} : *reinterpret_cast<const d2v*>(ur + i0 + 2);
+      a[0] += dv[0];
+      a[1] += dv[1];
+      b[0] += dv[2];
+      b[1] += dv[3];
+      *reinterpret_cast<d2v*>(ur + i0) = a;
+      *reinterpret_cast<d2v*>(ur + i0 + 2) = b;
+      const double m1 = fmax(fmax(fabs(static_cast<double>(dv[0])), fabs(static_cast<double>(dv[1]))),
+                             fmax(fabs(static_cast<double>(dv[2])), fabs(static_cast<double>(dv[3]))));
+      const double m2 = fmax(fmax(fabs(a[0]), fabs(a[1])), fmax(fabs(b[0]), fabs(b[1])));
+      bad = bad || !(m1 == m1) || !(m2 == m2);
+      dm = fmax(dm, m1);
+      um = fmax(um, m2);
+    } else {
+      for (long long i = i0; i < i0 + 4 && i < P; ++i) {
+        const double dv = dr[i];
+        const double un = (assign ? 0.0 : ur[i]) + dv;
+        ur[i] = un;
+        bad = bad || !(dv == dv) || !(un == un);
+        dm = fmax(dm, fabs(dv));
+        um = fmax(um, fabs(un));
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dm = fmax(dm, __shfl_xor(dm, o));
+    um = fmax(um, __shfl_xor(um, o));
+  }
+  const int wave = threadIdx.x >> 6;
+  const bool wbad = __any(bad);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wave] = dm;
+    sh[1][wave] = um;
+    shbad[wave] = wbad ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bd = 0.0, bu = 0.0;
+    int anybad = 0;
+    for (int w = 0; w < 4; ++w) {
+      bd = fmax(bd, sh[0][w]);
+      bu = fmax(bu, sh[1][w]);
+      anybad |= shbad[w];
+    }
+    atomic_max_nonneg(norm_slot(norms, r, 0), anybad ? __longlong_as_double(0x7ff8000000000000ll) : bd);
+    atomic_max_nonneg(norm_slot(norms, r, 1), bu);
+  }
+}
+
+hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign, unsigned long long* norms,
+                    hipStream_t st) {
+  if (P <= 0 || nrhs <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((P + 1023) / 1024, 2048);
+  hipLaunchKernelGGL(k_update, dim3(static_cast<unsigned>(blocks), nrhs), dim3(256), 0, st, u, d, P, assign, norms);
   return hipGetLastError();
 }
 

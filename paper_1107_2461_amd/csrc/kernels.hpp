@@ -9,7 +9,7 @@
 namespace helm {
 
 // Storage / compute types of the mode products.
-enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 /* split BF16, FP32 storage */ };
 
 // Epilogue of a mode product.
 enum Epi : int {
@@ -19,6 +19,10 @@ enum Epi : int {
 };
 
 constexpr int kMaxRhs = 64;
+// Refinement norms are accumulated with atomic max into kNormStripes slots per quantity (the
+// slot is chosen by workgroup index) to avoid same-address contention; layout
+// norms[(2 r + q) * kNormStripes + s], q = 0: max|du|, q = 1: max|u|, as FP64 bit patterns.
+constexpr int kNormStripes = 64;
 
 struct EpiArgs {
   const double* lamx = nullptr;   // eigenvalues of the x and y axes (divide epilogue)
@@ -26,7 +30,7 @@ struct EpiArgs {
   const double* lamz = nullptr;   // eigenvalues of the contracted (z) axis
   int nx = 1;                     // x extent, to split a column index into (b, a)
   int eq28 = 0;                   // zero denominator -> 1 (eq. 28) instead of projection
-  unsigned long long* norms = nullptr;  // [2 * nrhs]: max|du| bits, max|u| bits (accumulate)
+  unsigned long long* norms = nullptr;  // [2 * nrhs * kNormStripes] (accumulate), see kNormStripes
   long long rows_per_rhs = 1;     // rows of the x-mode matrix per RHS (accumulate)
   int accum_zero = 0;             // accumulate into zero instead of the current u
   double sigma[kMaxRhs];          // per-RHS shift
@@ -47,6 +51,16 @@ hipError_t mode_left(Prec p, const void* Msw, int K, const void* X, Prec tin, vo
 //   Y[m][a] = sum_i X[m][i] M[a][i],  m < Mrows, a < K.
 hipError_t mode_right(Prec p, const void* Msw, int K, const void* X, Prec tin, void* Y, Prec tout,
                       long long Mrows, Epi epi, const EpiArgs& ep, hipStream_t st);
+
+// Split-BF16 rotating-layout product (three bfloat16 pieces, six MFMA partial products,
+// FP32 accumulation and storage):  Y[r][a][pq] = sum_k M[a][k] X[r][pq][k],
+// r < R, pq < PQ, a < K.  Msw holds the three swizzled pieces of M, `piece` elements apart.
+// epi: STORE (FP32 Y), DIVIDE (FP32 Y, pq = b * nx + a_x, column a = the z index c) or
+// ACCUM (FP64 Y += result, with per-RHS norms).
+size_t swizzled_bf16x3_bytes(int K);
+void swizzle_bf16x3(int K, const double* M, void* out);
+hipError_t mode_rot(const void* Msw, int K, const float* X, void* Y, long long R, long long PQ, Epi epi,
+                    const EpiArgs& ep, hipStream_t st);
 
 // Batched Thomas solve along z (TPT, end of Section 3): for every RHS r and (b, a) line,
 // (K_z + c V_z) v = V_z g with c = lam_x[a] + lam_y[b] + sigma[r], in place on v (FP64).
@@ -82,6 +96,10 @@ struct StencilArgs {
 hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout,
                    const StencilArgs& a, hipStream_t st);
 
+// Refinement update u += d (or u = d when assign != 0) for nrhs fields of P points, d FP32,
+// with per-RHS max|d| and max|u| (bit patterns, atomic max) into norms[2 r], norms[2 r + 1].
+hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign, unsigned long long* norms,
+                    hipStream_t st);
 // Zero `n` 64-bit words (a fill kernel, safe under stream capture).
 hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st);
 // Volume-weighted mean removal per RHS: x -= sum(vol * x) * inv_volsum   (FP64, in place,

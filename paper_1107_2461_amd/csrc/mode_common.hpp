@@ -114,10 +114,19 @@ __device__ inline double column_shift(const EpiArgs& ep, long long n, int r) {
 }
 // Pointwise divide of eqs. 26-27 with the FP64 denominator lam_z(c) + shift; the exact zero
 // denominator of the all-Neumann null mode gives 0 (projection) or v (eq. 28: Lambda := 1).
+// FP64 reciprocal: hardware estimate refined by two Newton steps (error a few ulp), which is
+// much cheaper than a correctly rounded division inside an MFMA epilogue.
+__device__ inline double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
 __device__ inline double divide_by_eigs(double v, const EpiArgs& ep, int c, double shift) {
   const double den = ep.lamz[c] + shift;
   if (den == 0.0) return ep.eq28 ? v : 0.0;
-  return v / den;
+  return v * recip(den);
 }
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -125,6 +134,10 @@ __device__ inline double wave_max(double v) {
 }
 __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
   atomicMax(p, static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+// striped norm slot of quantity q (0: max|du|, 1: max|u|) of RHS r for this workgroup
+__device__ inline unsigned long long* norm_slot(unsigned long long* norms, long long r, int q) {
+  return norms + (2 * r + q) * kNormStripes + (blockIdx.x % kNormStripes);
 }
 
 // RHS index of row m of the x-mode matrix, given the RHS r_lo of the workgroup's first row.
@@ -143,7 +156,7 @@ struct NormAcc {
   __device__ inline void add(const EpiArgs& ep, long long r_lo, long long rr, double du, double un) {
     const double ad = fabs(du), au = fabs(un);
     if (!(ad == ad) || !(au == au)) {  // NaN: record it as the largest bit pattern
-      atomic_max_nonneg(ep.norms + 2 * rr, __longlong_as_double(0x7ff8000000000000ll));
+      atomic_max_nonneg(norm_slot(ep.norms, rr, 0), __longlong_as_double(0x7ff8000000000000ll));
       return;
     }
     if (rr == r_lo) {
@@ -153,8 +166,8 @@ struct NormAcc {
       dmax[1] = fmax(dmax[1], ad);
       umax[1] = fmax(umax[1], au);
     } else {
-      atomic_max_nonneg(ep.norms + 2 * rr, ad);
-      atomic_max_nonneg(ep.norms + 2 * rr + 1, au);
+      atomic_max_nonneg(norm_slot(ep.norms, rr, 0), ad);
+      atomic_max_nonneg(norm_slot(ep.norms, rr, 1), au);
     }
   }
   __device__ inline void flush(const EpiArgs& ep, long long r_lo, long long nrhs, int lane) {
@@ -162,8 +175,8 @@ struct NormAcc {
     for (int t = 0; t < 2; ++t) {
       const double dm = wave_max(dmax[t]), um = wave_max(umax[t]);
       if (lane == 0 && r_lo + t < nrhs) {
-        atomic_max_nonneg(ep.norms + 2 * (r_lo + t), dm);
-        atomic_max_nonneg(ep.norms + 2 * (r_lo + t) + 1, um);
+        atomic_max_nonneg(norm_slot(ep.norms, r_lo + t, 0), dm);
+        atomic_max_nonneg(norm_slot(ep.norms, r_lo + t, 1), um);
       }
     }
   }

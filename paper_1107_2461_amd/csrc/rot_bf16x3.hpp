@@ -1,0 +1,246 @@
+// Split-BF16 mode products with rotating layout (device templates).
+//
+// Every transform of eq. 29 is run as one GEMM form: the input is X[r][pq][k] (the
+// contracted axis k contiguous, pq a flattened pair of the other two axes, r the RHS) and
+// the output is Y[r][a][pq] = sum_k M[a][k] X[r][pq][k]: the contracted axis moves to the
+// front.  Three such rotations restore the natural order, so the six transforms
+//   x-fwd, y-fwd, z-fwd + divide, x-inv, y-inv, z-inv (+ update)
+// map [k][j][i] -> [a][k][j] -> [b][a][k] -> [c][b][a] -> [i][c][b] -> [j][i][c] -> [k][j][i],
+// each reading whole rows and writing 64-byte (FP32) or 128-byte (FP64) runs.  The inverse
+// transforms act on different axes and commute, so running them x, y, z keeps the rotation.
+//
+// Arithmetic: the operands are split into three bfloat16 pieces, v = v1 + v2 + v3 with
+// |v2| <~ 2^-8 |v1| and |v3| <~ 2^-16 |v1| (the eigenvector matrix once on the host, the FP32
+// data on the fly), and the six partial products with i + j <= 4 are accumulated on the
+// BF16 MFMA (16x16x32, FP32 accumulation), smallest first.  The dropped products are of
+// relative size 2^-24, so each product is FP32-accurate (the split-BF16 scheme of Henry,
+// Tang & Heinecke, ARITH 2019) at the BF16 matrix rate.  Intermediates are FP32.
+//
+// Workgroup: 4 waves; W of them span the K output columns (NB 16-wide blocks each), 4/W
+// span the MT rows (MB 16-row blocks each).  Per 32-wide k-block the workgroup loads its
+// MT x 32 FP32 input tile once (one 32-byte load per thread), splits it with the hardware
+// bfloat16 conversion and stores the three pieces in LDS in MFMA fragment order (double
+// buffered); every wave then reads its A fragments from LDS and its B fragments (the three
+// swizzled pieces of M, shared by all workgroups, L2-resident) from global memory.
+#pragma once
+
+#include "mode_common.hpp"
+
+namespace helm {
+
+typedef float f8v __attribute__((ext_vector_type(8)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_bits(float x) {
+  return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));  // v_cvt_pk_bf16_f32 (RNE)
+}
+__device__ inline float bf16_value(unsigned short h) { return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16); }
+
+// x = hi + mid + lo in bfloat16; the differences are exact in FP32.
+__device__ inline void split3(const f8v& x, u16x8& hi, u16x8& mid, u16x8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float v = x[j];
+    const unsigned short h = bf16_bits(v);
+    const float r1 = v - bf16_value(h);
+    const unsigned short m = bf16_bits(r1);
+    hi[j] = h;
+    mid[j] = m;
+    lo[j] = bf16_bits(r1 - bf16_value(m));
+  }
+}
+
+template <int W, int NB, int MB, int EPI, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict__ Msw, long long piece, int KB, int K,
+                                                       const float* __restrict__ X, void* __restrict__ Yv,
+                                                       long long R, long long PQ, EpiArgs ep) {
+  constexpr int WM = 4 / W;
+  constexpr int MT = WM * MB * 16;        // rows per workgroup
+  constexpr int RB = MT / 16;             // 16-row blocks per workgroup
+  constexpr int CHUNKS = RB * 64;         // 8-element chunks per k-block tile
+  constexpr int CPT = (CHUNKS + 255) / 256;
+  __shared__ u16x8 lds[2][3][RB * 64];    // [buffer][piece][row block * 64 + lane]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wn = wave % W, wm = wave / W;
+  const int l16 = lane & 15, g = lane >> 4;
+  const long long Mrows = R * PQ;
+  const long long mwg = static_cast<long long>(blockIdx.x) * MT;
+  const int cb0 = wn * NB;
+  const int rb0 = wm * MB;                // this wave's first row block inside the tile
+
+  // producer assignment: chunk c -> row block c / 64, fragment lane c % 64
+  const float* src[CPT];
+  bool srcok[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int c = tid + q * 256;
+    const int rb = c >> 6, ln = c & 63;
+    const long long row = mwg + rb * 16 + (ln & 15);
+    srcok[q] = c < CHUNKS && row < Mrows;
+    src[q] = X + (srcok[q] ? row : 0) * K + 8 * (ln >> 4);
+  }
+  auto load_tile = [&](int kb, f8v (&v)[CPT]) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int kq = kb * 32 + 8 * (((tid + q * 256) & 63) >> 4);
+      if constexpr (VEC) {
+        if (srcok[q] && kq < K) {
+          v[q] = *reinterpret_cast<const f8v*>(src[q] + kb * 32);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[q][j] = 0.f;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[q][j] = (srcok[q] && kq + j < K) ? src[q][kb * 32 + j] : 0.f;
+      }
+    }
+  };
+  auto store_tile = [&](int buf, const f8v (&v)[CPT]) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = tid + q * 256;
+      if (c < CHUNKS) {
+        u16x8 h, m, l;
+        split3(v[q], h, m, l);
+        lds[buf][0][c] = h;
+        lds[buf][1][c] = m;
+        lds[buf][2][c] = l;
+      }
+    }
+  };
+
+  f4 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
+
+  // B fragments (the three pieces of M) of one k-block for this wave's NB column blocks
+  auto load_b = [&](int kb, u16x8 (&b)[NB][3]) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const long long o = ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 8;
+      b[nb][0] = *reinterpret_cast<const u16x8*>(Msw + o);
+      b[nb][1] = *reinterpret_cast<const u16x8*>(Msw + piece + o);
+      b[nb][2] = *reinterpret_cast<const u16x8*>(Msw + 2 * piece + o);
+    }
+  };
+  // input tiles kb+1 .. kb+DEPTH are in flight in registers while k-block kb is multiplied,
+  // so the HBM latency is covered by DEPTH k-blocks of MFMA work
+  constexpr int DEPTH = 2;
+  f8v stage[DEPTH][CPT];
+  u16x8 bcur[NB][3];
+  load_tile(0, stage[0]);
+  store_tile(0, stage[0]);
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d)
+    if (1 + d < KB) load_tile(1 + d, stage[d]);
+  __syncthreads();
+  for (int kb = 0; kb < KB; ++kb) {
+    const int buf = kb & 1;
+    // B fragments of all NB column blocks stay in registers; the row blocks' A fragments are
+    // read from LDS one block at a time, so a wave can cover many rows per L2 read of M
+    load_b(kb, bcur);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int c = (rb0 + mb) * 64 + lane;
+      const u16x8 a1 = lds[buf][0][c], a2 = lds[buf][1][c], a3 = lds[buf][2][c];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        f4 v = acc[mb][nb];
+        v = mma_bf16(a3, bcur[nb][0], v);
+        v = mma_bf16(a2, bcur[nb][1], v);
+        v = mma_bf16(a1, bcur[nb][2], v);
+        v = mma_bf16(a2, bcur[nb][0], v);
+        v = mma_bf16(a1, bcur[nb][1], v);
+        v = mma_bf16(a1, bcur[nb][0], v);
+        acc[mb][nb] = v;
+      }
+    }
+    if (kb + 1 < KB) {
+      store_tile(buf ^ 1, stage[0]);
+#pragma unroll
+      for (int d = 0; d + 1 < DEPTH; ++d)
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) stage[d][q] = stage[d + 1][q];
+      if (kb + 1 + DEPTH < KB) load_tile(kb + 1 + DEPTH, stage[DEPTH - 1]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds rows m = mwg + (rb0 + mb)*16 + 4g + t (t < 4), column a = (cb0 + nb)*16 + l16
+  const long long r_lo = mwg / PQ;
+  [[maybe_unused]] NormAcc na;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;  // first of the lane's four rows
+    long long rr[4], pq[4];
+    [[maybe_unused]] double shift[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      rr[t] = rhs_of_row(mq + t, r_lo, PQ);
+      pq[t] = mq + t - rr[t] * PQ;
+      if constexpr (EPI == EPI_DIVIDE) {
+        const int pqi = static_cast<int>(pq[t]);
+        const int b = pqi / ep.nx;
+        shift[t] = (mq + t < Mrows) ? ep.lamx[pqi - b * ep.nx] + ep.lamy[b] + ep.sigma[rr[t]] : 1.0;
+      }
+    }
+    const bool full = VEC && (mq + 3 < Mrows);  // the four rows share one RHS and are aligned
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int a = (cb0 + nb) * 16 + l16;
+      if (a >= K) continue;
+      if constexpr (EPI == EPI_ACCUM) {
+        double* Y = static_cast<double*>(Yv);
+        if (full) {
+          d4v* p = reinterpret_cast<d4v*>(Y + (rr[0] * K + a) * PQ + pq[0]);
+          d4v un = ep.accum_zero ? d4v{0, 0, 0, 0} : *p;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double du = static_cast<double>(acc[mb][nb][t]);
+            un[t] += du;
+            na.add(ep, r_lo, rr[0], du, un[t]);
+          }
+          *p = un;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (mq + t >= Mrows) continue;
+            const long long idx = (rr[t] * K + a) * PQ + pq[t];
+            const double du = static_cast<double>(acc[mb][nb][t]);
+            const double un = (ep.accum_zero ? 0.0 : Y[idx]) + du;
+            Y[idx] = un;
+            na.add(ep, r_lo, rr[t], du, un);
+          }
+        }
+      } else {
+        float* Y = static_cast<float*>(Yv);
+        f4 v = acc[mb][nb];
+        if constexpr (EPI == EPI_DIVIDE) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            v[t] = static_cast<float>(divide_by_eigs(static_cast<double>(v[t]), ep, a, shift[t]));
+        }
+        if (full) {
+          *reinterpret_cast<f4*>(Y + (rr[0] * K + a) * PQ + pq[0]) = v;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (mq + t < Mrows) Y[(rr[t] * K + a) * PQ + pq[t]] = v[t];
+        }
+      }
+    }
+  }
+  if constexpr (EPI == EPI_ACCUM) na.flush(ep, r_lo, R, lane);
+}
+
+// Row blocks per wave for the rotating kernel with table entry c: 128-row workgroup tiles
+// (64 for the widest entry), so the double-buffered split tile (6 bytes per element) takes at
+// most 48 KB of LDS and each L2 read of M serves 128 rows.
+constexpr int rot_rows(Cfg c) { return c.W == 4 ? (c.MB >= 8 ? 2 : 8) : (c.W == 2 ? 4 : 2); }
+
+}  // namespace helm

@@ -39,6 +39,7 @@ struct DevAxis {
   double* E = nullptr;       // m*m row-major
   double* Einv = nullptr;    // m*m row-major
   void* sw[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][fwd, inv]
+  void* sw3[2] = {nullptr, nullptr};  // split-BF16 pieces [fwd, inv]
   ~DevAxis() {
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -48,6 +49,8 @@ struct DevAxis {
     for (auto& pr : sw)
       for (void* p : pr)
         if (p) (void)hipFree(p);
+    for (void* p : sw3)
+      if (p) (void)hipFree(p);
     (void)hipSetDevice(cur);
   }
 };
@@ -120,6 +123,14 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
       e = upload(reinterpret_cast<unsigned char**>(&ax->sw[p][dir]), buf.data(), bytes);
     }
   }
+  if (e == hipSuccess) {
+    const size_t bytes = swizzled_bf16x3_bytes(m);
+    std::vector<unsigned char> buf(bytes);
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+      swizzle_bf16x3(m, dir == 0 ? h.Einv.data() : h.E.data(), buf.data());
+      e = upload(reinterpret_cast<unsigned char**>(&ax->sw3[dir]), buf.data(), bytes);
+    }
+  }
   if (e != hipSuccess) return from_hip(e);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -175,20 +186,24 @@ struct helm_plan {
   helm_opts opts{};
   bool all_neumann = false;
   int device = 0;
-  unsigned long long* host_norms = nullptr;  // pinned, 2 * kMaxRhs
+  unsigned long long* host_norms = nullptr;  // pinned, 2 * kMaxRhs * kNormStripes
   std::mutex mu;                             // guards host_norms
   mutable StageProfiler prof;
   ~helm_plan() {
     if (host_norms) (void)hipHostFree(host_norms);
   }
   long long npts() const { return static_cast<long long>(m[0]) * m[1] * m[2]; }
-  bool refined() const { return opts.precision == HELM_FP32_IR || opts.precision == HELM_BF16_IR; }
+  bool refined() const {
+    return opts.precision == HELM_FP32_IR || opts.precision == HELM_BF16_IR || opts.precision == HELM_BF16X3_IR;
+  }
   Prec prec() const {
     switch (opts.precision) {
       case HELM_FP32:
       case HELM_FP32_IR: return P_F32;
       case HELM_BF16:
       case HELM_BF16_IR: return P_BF16;
+      case HELM_BF16X3:
+      case HELM_BF16X3_IR: return P_BF16X3;
       default: return P_F64;
     }
   }
@@ -243,7 +258,7 @@ helm_status helm_host_eigen_1d(int n, const double* faces, int loc, int bc_lo, i
 }
 
 static bool valid_opts(const helm_opts& o) {
-  if (o.precision < HELM_FP64 || o.precision > HELM_BF16_IR) return false;
+  if (o.precision < HELM_FP64 || o.precision > HELM_BF16X3_IR) return false;
   if (o.method != HELM_TPF && o.method != HELM_TPT_Z) return false;
   if (o.null_mode != HELM_NULL_PROJECT && o.null_mode != HELM_NULL_PAPER_EQ28) return false;
   if (!(o.ir_tol > 0.0) || o.max_sweeps < 1) return false;
@@ -291,8 +306,8 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
   }
   p->all_neumann = alln;
   if (has_zero_denominator(p.get(), sigma)) return HELM_ESINGULAR;
-  if (hipHostMalloc(reinterpret_cast<void**>(&p->host_norms), 2 * kMaxRhs * sizeof(unsigned long long)) !=
-      hipSuccess)
+  if (hipHostMalloc(reinterpret_cast<void**>(&p->host_norms),
+                    2 * kMaxRhs * kNormStripes * sizeof(unsigned long long)) != hipSuccess)
     return HELM_ENOMEM;
   *out = p.release();
   return HELM_OK;
@@ -312,13 +327,13 @@ static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t
     if (p->opts.method == HELM_TPT_Z) t += align_up(thomas_scratch_bytes(p->m[0], p->m[1], p->m[2], nrhs), 256);
     *off_norms = t;
   } else {
-    const size_t es = p->prec() == P_F32 ? 4 : 2;
+    const size_t es = p->prec() == P_BF16 ? 2 : 4;
     *off_a = 0;
     t = align_up(P * es, 256);
     *off_b = t;
     t += align_up(P * es, 256);
     *off_norms = t;
-    t += align_up(2 * kMaxRhs * sizeof(unsigned long long), 256);
+    t += align_up(2 * kMaxRhs * kNormStripes * sizeof(unsigned long long), 256);
   }
   if (off_mean) *off_mean = t;
   if (p->all_neumann) t += align_up(static_cast<size_t>(nrhs) * (kMeanBlocks + 1) * sizeof(double), 256);
@@ -400,8 +415,43 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   ep.rows_per_rhs = ny * nz;
   ep.accum_zero = accum_zero;
   for (int r = 0; r < nrhs; ++r) ep.sigma[r] = sig[r];
-  const int ip = static_cast<int>(pr);
   hipError_t e;
+  if (pr == P_BF16X3) {
+    // rotating layout: [k][j][i] -> [a][k][j] -> [b][a][k] -> [c][b][a] -> [i][c][b] -> [j][i][c] -> [k][j][i]
+    const float* fin = static_cast<const float*>(in);
+    float* f1 = static_cast<float*>(b1);
+    float* f2 = static_cast<float*>(b2);
+    if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
+           return mode_rot(X.sw3[0], nx, fin, f1, nrhs, ny * nz, EPI_STORE, ep, st);
+         })) != hipSuccess)
+      return e;
+    if ((e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
+           return mode_rot(Y.sw3[0], ny, f1, f2, nrhs, nz * nx, EPI_STORE, ep, st);
+         })) != hipSuccess)
+      return e;
+    if ((e = timed(p, HELM_STAGE_Z_FWD_DIV, st, [&] {
+           return mode_rot(Z.sw3[0], nz, f2, f1, nrhs, nx * ny, EPI_DIVIDE, ep, st);
+         })) != hipSuccess)
+      return e;
+    if ((e = timed(p, HELM_STAGE_X_INV, st, [&] {
+           return mode_rot(X.sw3[1], nx, f1, f2, nrhs, nz * ny, EPI_STORE, ep, st);
+         })) != hipSuccess)
+      return e;
+    if ((e = timed(p, HELM_STAGE_Y_INV, st, [&] {
+           return mode_rot(Y.sw3[1], ny, f2, f1, nrhs, nx * nz, EPI_STORE, ep, st);
+         })) != hipSuccess)
+      return e;
+    // the correction lands in FP32 (natural layout) and is added to u by a streaming kernel
+    if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
+           return mode_rot(Z.sw3[1], nz, f1, f2, nrhs, ny * nx, EPI_STORE, ep, st);
+         })) != hipSuccess)
+      return e;
+    if (epi_last != EPI_ACCUM) return hipErrorInvalidValue;
+    return timed(p, HELM_STAGE_UPDATE, st, [&] {
+      return update_u(static_cast<double*>(out), f2, nx * ny * nz, nrhs, accum_zero, norms, st);
+    });
+  }
+  const int ip = static_cast<int>(pr);
   // forward: E_x^{-1}, E_y^{-1}, E_z^{-1} + divide
   if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
          return mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, ep, st);
@@ -569,9 +619,10 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   void* L2 = w + off_b;
   unsigned long long* norms = reinterpret_cast<unsigned long long*>(w + off_n);
   const StencilArgs sa = stencil_args(p, nrhs, sig);
+  const Prec store = pr == P_BF16X3 ? P_F32 : pr;  // storage type of the low-precision fields
   // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.
-  if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs, st); });
-  if (e == hipSuccess) e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, pr, sa, st); });
+  if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
+  if (e == hipSuccess) e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, store, sa, st); });
   if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st);
   if (e != hipSuccess) return from_hip(e);
   if (!p->refined()) return from_hip(project_null());
@@ -580,20 +631,27 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   double last = 0.0, prev = 1.0;  // the first solve's "correction" is u itself
   bool conv = false;
   while (sweeps < p->opts.max_sweeps) {
-    if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs, st); });
-    if (e == hipSuccess) e = timed(p, HELM_STAGE_RESIDUAL, st, [&] { return stencil(1, u, f, L1, pr, sa, st); });
+    if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
+    if (e == hipSuccess) e = timed(p, HELM_STAGE_RESIDUAL, st, [&] { return stencil(1, u, f, L1, store, sa, st); });
     if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(p->host_norms, norms, 2 * nrhs * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(p->host_norms, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return from_hip(e);
     ++sweeps;
     last = 0.0;
     bool finite = true;
     for (int r = 0; r < nrhs; ++r) {
+      // the stripes hold non-negative FP64 bit patterns (NaN as the largest): integer max
+      unsigned long long bd = 0, bu = 0;
+      for (int q = 0; q < kNormStripes; ++q) {
+        bd = std::max(bd, p->host_norms[(2 * r) * kNormStripes + q]);
+        bu = std::max(bu, p->host_norms[(2 * r + 1) * kNormStripes + q]);
+      }
       double dm, um;
-      std::memcpy(&dm, &p->host_norms[2 * r], 8);
-      std::memcpy(&um, &p->host_norms[2 * r + 1], 8);
+      std::memcpy(&dm, &bd, 8);
+      std::memcpy(&um, &bu, 8);
       if (!std::isfinite(dm) || !std::isfinite(um)) finite = false;
       const double rel = um > 0.0 ? dm / um : (dm > 0.0 ? INFINITY : 0.0);
       last = std::max(last, rel);

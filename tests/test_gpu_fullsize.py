@@ -71,7 +71,8 @@ def test_mixed_256_paths(torch):
     g = _golden("c3")
     fd = torch.from_numpy(f).cuda()
     out = {}
-    for precision, tol in (("fp64", 1e-12), ("fp32_ir", 1e-10), ("bf16_ir", 1e-10), ("fp32", 1e-5), ("bf16", 1e-2)):
+    for precision, tol in (("fp64", 1e-12), ("fp32_ir", 1e-10), ("bf16_ir", 1e-10), ("bf16x3_ir", 1e-10),
+                           ("fp32", 1e-5), ("bf16", 1e-2), ("bf16x3", 1e-5)):
         plan = _plan(prob, precision=precision)
         u = plan.solve(fd)
         torch.cuda.synchronize()
@@ -89,7 +90,7 @@ def test_mixed_256_error_per_sweep(torch):
     prob, f = workloads.workload_mixed_256()
     g = _golden("c3")
     fd = torch.from_numpy(f).cuda()
-    for precision in ("fp32_ir", "bf16_ir"):
+    for precision in ("fp32_ir", "bf16_ir", "bf16x3_ir"):
         errs = []
         for k in range(1, 9):
             plan = _plan(prob, precision=precision, max_sweeps=k, ir_tol=1e-300)
@@ -109,7 +110,7 @@ def test_pressure_192x160x224_mixed(torch):
     prob, f = workloads.workload_pressure()
     g = _golden("c4_pressure")
     fd = torch.from_numpy(f).cuda()
-    for precision, tol in (("fp64", 1e-11), ("bf16_ir", 1e-10)):
+    for precision, tol in (("fp64", 1e-11), ("bf16_ir", 1e-10), ("bf16x3_ir", 1e-10)):
         plan = Plan(prob.faces, pressure=True, precision=precision)
         u = plan.solve(fd)
         torch.cuda.synchronize()

@@ -124,7 +124,8 @@ def test_pressure_plan_entry_point(torch):
     assert _per_rhs_err(u, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 1e-2), ("fp32_ir", 1e-10), ("bf16_ir", 1e-10)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 1e-2), ("bf16x3", 1e-5), ("fp32_ir", 1e-10),
+                                           ("bf16_ir", 1e-10), ("bf16x3_ir", 1e-10)])
 def test_low_precision_and_refinement(torch, precision, tol):
     prob = workloads.box_problem((40, 36, 44), 1.5, sigma=0.1)
     f = workloads.rhs_normal(3, 2, prob.shape_xyz)
@@ -135,15 +136,31 @@ def test_low_precision_and_refinement(torch, precision, tol):
     assert err <= tol
 
 
-def test_refinement_neumann_laplace(torch):
+@pytest.mark.parametrize("case", range(len(RAGGED)))
+def test_ragged_mixed_bc_split_bf16_refined(torch, case):
+    """Split-BF16 products with refinement on ragged, staggered, multi-RHS problems (tails of
+    every tile, rows not multiple of 8, per-RHS shifts including a Laplace RHS)."""
+    n, betas, lo, hi, loc = RAGGED[case]
+    faces = tuple(workloads.stretched_faces(n[d], betas[d]) for d in range(3))
+    prob = workloads.Problem(faces=faces, bc_lo=lo, bc_hi=hi, loc=loc, sigma=0.7)
+    sig = [0.7, 3.0e2, 0.0]
+    f = workloads.rhs_uniform(31 + case, 3, prob.shape_xyz)
+    u, plan = _solve(torch, prob, f, sigma=sig, precision="bf16x3_ir")
+    ref = _oracle(prob, f, sigma=sig, method="splu")
+    assert plan.last_info["converged"]
+    assert _per_rhs_err(u, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["bf16_ir", "bf16x3_ir", "fp32_ir"])
+def test_refinement_neumann_laplace(torch, precision):
     n = (32, 28, 36)
     faces = tuple(workloads.stretched_faces(n[d], 2.0) for d in range(3))
     prob = workloads.Problem(faces=faces, bc_lo=(N,) * 3, bc_hi=(N,) * 3, sigma=0.0)
     f = workloads.remove_weighted_mean(workloads.rhs_uniform(5, 1, prob.shape_xyz), faces)
-    u, plan = _solve(torch, prob, f, precision="bf16_ir")
+    u, plan = _solve(torch, prob, f, precision=precision)
     ref = _oracle(prob, f, method="splu")
     assert plan.last_info["converged"]
-    assert _per_rhs_err(_gauge(u, faces), ref) <= 1e-10
+    assert _per_rhs_err(u, ref) <= 1e-10          # the solver returns the zero-mean gauge
 
 
 def test_apply_matches_oracle_operator(torch):
