@@ -176,6 +176,75 @@ def cpu_baseline(prob, f, golden, budget_s):
                 seconds_per_solve=t_solve)
 
 
+def run_serving(torch, args):
+    """Serving stream: Poisson arrivals of mixed solve requests through the continuous-batching server."""
+    from paper_1107_2461_amd import Server
+    n_warm, n_meas = args.serve_warmup, args.serve_requests
+    reqs = workloads.serving_requests(5, n_warm + n_meas, rate_hz=1.0)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    pool = {}
+    for g in workloads.SERVING_GRIDS:
+        nx, ny, nz = g
+        pool[g] = torch.randn((3, nz, ny, nx), generator=gen, device="cuda", dtype=torch.float64)
+    probs = [workloads.serving_problem(r) for r in reqs]
+
+    def stream(srv, idx, times):
+        """Submit requests idx at relative times (seconds); return the completion records."""
+        outs = {}
+        t0 = srv.now()
+        recs = []
+        for i, t in zip(idx, times):
+            while srv.now() - t0 < t:
+                recs += srv.poll(wait_ms=0)
+            r = reqs[i]
+            f = pool[tuple(r["n"])][: r["nrhs"]]
+            u = torch.empty_like(f)
+            outs[i] = u
+            srv.submit(i, probs[i].faces, f, u, [r["sigma"]] * r["nrhs"], r["bc_lo"], r["bc_hi"])
+            recs += srv.poll(wait_ms=0)
+        srv.drain()
+        recs += srv.poll(max_records=len(idx) + 16)
+        return recs
+
+    out = {}
+    for prec in args.serve_paths.split(","):
+        srv = Server(args.serve_budget_gb << 30, slots=args.serve_slots, precision=prec, max_bypass_ms=20.0)
+        # warm the resident plan cache, then measure the closed-loop service rate with warm plans
+        warm = list(range(n_warm))
+        stream(srv, warm, [0.0] * n_warm)
+        t0 = time.perf_counter()
+        stream(srv, warm, [0.0] * n_warm)
+        cap = n_warm / (time.perf_counter() - t0)
+        rate = args.serve_load * cap
+        rng = np.random.default_rng(55)
+        times = np.cumsum(rng.exponential(1.0 / rate, n_meas))
+        idx = list(range(n_warm, n_warm + n_meas))
+        recs = stream(srv, idx, times)
+        srv.close()
+        bad = [r for r in recs if r["status"] != 0]
+        lat = np.array([r["t_done"] - r["t_submit"] for r in recs])
+        wait = np.array([r["t_admit"] - r["t_submit"] for r in recs])
+        pts = sum(reqs[r["id"]]["n"][0] * reqs[r["id"]]["n"][1] * reqs[r["id"]]["n"][2] * reqs[r["id"]]["nrhs"]
+                  for r in recs)
+        span = max(r["t_done"] for r in recs) - min(r["t_submit"] for r in recs)
+        out[prec] = dict(requests=len(recs), failed=len(bad), offered_rate_hz=rate, closed_loop_rate_hz=cap,
+                         pts_per_s=pts / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
+                         p99_ms=float(np.percentile(lat, 99) * 1e3), mean_queue_ms=float(wait.mean() * 1e3),
+                         mean_sweeps=float(np.mean([r["sweeps"] for r in recs])))
+        log(f"[serve] {prec}: {out[prec]}")
+    best = max(out, key=lambda k: out[k]["pts_per_s"])
+    line = dict(metric="grid-pts/s per Helmholtz solve @1e-10 rel err (serving stream); p50/p99 latency",
+                value=out[best]["pts_per_s"], unit="grid-pts/s", n_gpus=1, steps=n_meas, warmup=n_warm,
+                ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="bf16x3" if best.startswith("bf16x3") else "f64", data="synthetic",
+                config=dict(workload="serving stream: grids 64^3..256^3, tanh stretch 1.0-2.0, tau 10^U(-3,2), "
+                                     "1 or 3 RHS, mixed D/N walls, 20% Laplace",
+                            path=best, slots=args.serve_slots, hbm_budget_gb=args.serve_budget_gb,
+                            offered_load=args.serve_load),
+                p50_ms=out[best]["p50_ms"], p99_ms=out[best]["p99_ms"], paths=out)
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +254,12 @@ def main():
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=300)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=int, default=16)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-paths", default="bf16x3_ir,fp64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps(dict(error="this solver benchmark runs on exactly one GPU; the multi-GPU (z-slab + "
@@ -196,6 +271,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     from paper_1107_2461_amd import load
     load()
+    if args.workload == "serving":
+        run_serving(torch, args)
+        return
     prob, f, gname, extra = build_workload(args.workload)
     golden = None
     if gname:

@@ -193,6 +193,60 @@ enum {
 helm_status helm_profile_enable(helm_plan* plan, int enable);
 helm_status helm_profile_read(helm_plan* plan, double* ms, int* launches);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of solve requests on one GPU.
+ *
+ * Requests (grid, walls, per-RHS shifts, 1..64 right-hand sides, caller-owned device f and u)
+ * are queued on submit.  A scheduler thread admits queued requests in arrival order while
+ * (a) a solve slot is free and (b) the sum of the device workspace of the admitted requests
+ * stays within the HBM budget; a request that does not fit waits until running requests
+ * retire (a later, smaller request may pass it only if the head has waited less than
+ * `max_bypass_ms`).  Each slot owns a HIP stream and a host worker thread, so admitted
+ * solves run concurrently on the device and new requests are admitted while others are in
+ * flight.  Plans (1D eigenbases) are cached on the device by their axis definition and
+ * reused across requests.  Times are seconds since server creation (steady clock).
+ * --------------------------------------------------------------------------------------- */
+typedef struct helm_server helm_server;
+
+typedef struct {
+  long long id;            /* caller's request id */
+  int status;              /* helm_status of the solve */
+  int sweeps;              /* refinement sweeps used */
+  double last_correction;  /* final refinement correction */
+  double t_submit;         /* submit time */
+  double t_admit;          /* admission time */
+  double t_done;           /* completion time (device work finished) */
+  size_t footprint;        /* device workspace bytes charged against the budget */
+  int slot;                /* slot that ran it */
+} helm_request_record;
+
+/* Creates a server with `slots` concurrent solve slots (1..16) and a device-workspace budget
+ * of hbm_budget_bytes; opts sets the arithmetic of every solve (NULL = FP64 TPF). */
+helm_status helm_server_create(size_t hbm_budget_bytes, int slots, double max_bypass_ms, const helm_opts* opts,
+                               helm_server** out);
+/* Queues one request; returns at once.  f, u: device [nrhs][nz][ny][nx] float64 owned by the
+ * caller, untouched until the request's record is returned by helm_server_poll.  sigma: host
+ * array of nrhs shifts (copied).  Errors: EINVAL (bad arguments, or a footprint larger than
+ * the whole budget, which could never be admitted). */
+helm_status helm_server_submit(helm_server* s, const helm_grid* grid, const helm_bc* bc, const double* sigma,
+                               int nrhs, const double* f, double* u, long long id);
+/* Returns up to max completed-request records (oldest first) in out and their count in *n,
+ * waiting up to wait_ms milliseconds for at least one (0 = do not wait). */
+helm_status helm_server_poll(helm_server* s, helm_request_record* out, int max, int* n, int wait_ms);
+/* Blocks until every submitted request has completed (its record stays pollable). */
+helm_status helm_server_drain(helm_server* s);
+/* Current time on the server clock (seconds since creation). */
+double helm_server_now(const helm_server* s);
+/* Drains, stops the threads and releases the server (cached plans stay until process exit). */
+void helm_server_destroy(helm_server* s);
+
+/* Host-only simulation of the admission policy on a virtual clock (no device): n requests
+ * with arrival times arrival[i], service times service[i] and footprints foot[i] are
+ * scheduled on `slots` slots under `budget`; outputs the admission and completion times.
+ * Runs the same admission code as the server.  Errors: EINVAL. */
+helm_status helm_sched_simulate(int n, const double* arrival, const double* service, const size_t* foot,
+                                int slots, size_t budget, double max_bypass_ms, double* admit, double* done);
+
 /* Host-only helpers (no device needed), for checking the setup stage on any machine. */
 /* 1D operator of one axis: lower/diag/upper rows of A = V^{-1} K (each of length m, the
  * number of unknowns) and the control-volume widths vol[m].  Returns m in *m_out. */

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (BF16, BF16_IR, CELL, DIRICHLET, FACE, FP32, FP32_IR, FP64, NEUMANN, NULL_PAPER_EQ28,
                    NULL_PROJECT, TPF, TPT_Z, HelmError, check, load)
 
-__all__ = ["Plan", "PressureMatrix", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
+__all__ = ["Plan", "PressureMatrix", "Server", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
            "NEUMANN", "CELL", "FACE", "FP64", "FP32", "BF16", "FP32_IR", "BF16_IR", "TPF", "TPT_Z",
            "NULL_PROJECT", "NULL_PAPER_EQ28"]
 
@@ -265,3 +265,79 @@ class PressureMatrix:
         if st not in (_lib.HELM_OK, _lib.HELM_ENOTCONVERGED):
             check(st, "helm_pmatrix_solve")
         return p
+
+
+class Server:
+    """Continuous-batching solve server (helm_server_*): submit requests, poll completions."""
+
+    def __init__(self, budget_bytes, slots=4, precision="fp64", max_bypass_ms=50.0, method="tpf"):
+        lib = load()
+        opts = _opts(precision, method, None, None, NULL_PROJECT)
+        h = C.c_void_p()
+        check(lib.helm_server_create(int(budget_bytes), int(slots), float(max_bypass_ms), C.byref(opts), C.byref(h)),
+              "helm_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, rid, faces, f, u, sigma, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, loc=(CELL,) * 3):
+        """Queue one request; f, u: contiguous float64 CUDA tensors [nrhs, nz, ny, nx]; sigma: nrhs shifts."""
+        g, arrs = _grid(faces, loc)
+        bc = _lib.HelmBC()
+        for d in range(3):
+            bc.lo[d] = int(bc_lo[d])
+            bc.hi[d] = int(bc_hi[d])
+        nrhs = f.shape[0]
+        sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (nrhs,)))
+        self._live[int(rid)] = (f, u)
+        st = load().helm_server_submit(self._h, C.byref(g), C.byref(bc), sig.ctypes.data_as(_lib.DP), int(nrhs),
+                                       C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), int(rid))
+        if st != _lib.HELM_OK:
+            self._live.pop(int(rid), None)
+            check(st, "helm_server_submit")
+
+    def poll(self, max_records=256, wait_ms=0):
+        recs = (_lib.HelmRequestRecord * max_records)()
+        n = C.c_int()
+        check(load().helm_server_poll(self._h, recs, max_records, C.byref(n), int(wait_ms)), "helm_server_poll")
+        out = []
+        for i in range(n.value):
+            r = recs[i]
+            self._live.pop(r.id, None)
+            out.append(dict(id=r.id, status=r.status, sweeps=r.sweeps, last_correction=r.last_correction,
+                            t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done, footprint=r.footprint,
+                            slot=r.slot))
+        return out
+
+    def drain(self):
+        check(load().helm_server_drain(self._h), "helm_server_drain")
+
+    def now(self):
+        return load().helm_server_now(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().helm_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sched_simulate(arrival, service, footprint, slots, budget, max_bypass_ms=0.0):
+    """Admission policy of the server on a virtual clock (host only): returns (admit, done) times."""
+    lib = load()
+    arr = np.ascontiguousarray(np.asarray(arrival, dtype=np.float64))
+    srv = np.ascontiguousarray(np.asarray(service, dtype=np.float64))
+    ft = np.ascontiguousarray(np.asarray(footprint, dtype=np.uint64))
+    n = len(arr)
+    admit = np.zeros(n)
+    done = np.zeros(n)
+    check(lib.helm_sched_simulate(n, arr.ctypes.data_as(_lib.DP), srv.ctypes.data_as(_lib.DP),
+                                  ft.ctypes.data_as(C.POINTER(C.c_size_t)), int(slots), int(budget),
+                                  float(max_bypass_ms), admit.ctypes.data_as(_lib.DP), done.ctypes.data_as(_lib.DP)),
+          "helm_sched_simulate")
+    return admit, done

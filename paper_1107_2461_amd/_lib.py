@@ -39,6 +39,12 @@ class HelmInfo(C.Structure):
                 ("iterations", C.c_int), ("residual", C.c_double)]
 
 
+class HelmRequestRecord(C.Structure):
+    _fields_ = [("id", C.c_longlong), ("status", C.c_int), ("sweeps", C.c_int), ("last_correction", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint", C.c_size_t),
+                ("slot", C.c_int)]
+
+
 P = C.c_void_p
 DP = C.POINTER(C.c_double)
 IP = C.POINTER(C.c_int)
@@ -64,6 +70,14 @@ SIGNATURES = {
     "helm_pmatrix_destroy": (None, [P]),
     "helm_profile_enable": (C.c_int, [P, C.c_int]),
     "helm_profile_read": (C.c_int, [P, DP, IP]),
+    "helm_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_double, C.POINTER(HelmOpts), C.POINTER(P)]),
+    "helm_server_submit": (C.c_int, [P, C.POINTER(HelmGrid), C.POINTER(HelmBC), DP, C.c_int, P, P, C.c_longlong]),
+    "helm_server_poll": (C.c_int, [P, C.POINTER(HelmRequestRecord), C.c_int, IP, C.c_int]),
+    "helm_server_drain": (C.c_int, [P]),
+    "helm_server_now": (C.c_double, [P]),
+    "helm_server_destroy": (None, [P]),
+    "helm_sched_simulate": (C.c_int, [C.c_int, DP, DP, C.POINTER(C.c_size_t), C.c_int, C.c_size_t, C.c_double, DP,
+                                      DP]),
     "helm_host_operator_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
     "helm_host_eigen_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP]),
 }

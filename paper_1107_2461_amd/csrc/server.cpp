@@ -1,0 +1,332 @@
+// Continuous-batching solve server (include/helm.h, "Serving").
+//
+// The time-stepping use of the solver (Section 5, eqs. 37-40) issues a stream of Helmholtz
+// and Poisson solves of different shifts and right-hand-side counts, whose cost does not
+// depend on the time step (Section 1).  The server keeps the eigenbases resident, admits
+// queued requests by free slot and device-workspace budget, and runs each admitted request on
+// its slot's stream from the slot's worker thread, so requests overlap on the GPU and new
+// ones are admitted while others are in flight.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/helm.h"
+
+namespace {
+
+// ---------------------------------------------------------------- admission policy
+struct Pending {
+  double t_submit;
+  size_t foot;
+};
+
+// Index (in the arrival-ordered queue) of the next request to admit, or -1.  The head is
+// admitted when it fits; otherwise a later request that fits may pass it only while the head
+// has waited less than max_bypass (after that, capacity is reserved for the head).
+template <typename Q>
+int pick_next(const Q& queue, int free_slots, size_t used, size_t budget, double now, double max_bypass) {
+  if (free_slots <= 0 || queue.empty()) return -1;
+  if (used + queue.front().foot <= budget) return 0;
+  if (now - queue.front().t_submit >= max_bypass) return -1;
+  for (size_t i = 1; i < queue.size(); ++i)
+    if (used + queue[i].foot <= budget) return static_cast<int>(i);
+  return -1;
+}
+
+struct Request {
+  long long id = 0;
+  helm_plan* plan = nullptr;
+  std::vector<double> sigma;
+  int nrhs = 0;
+  const double* f = nullptr;
+  double* u = nullptr;
+  double t_submit = 0.0, t_admit = 0.0;
+  size_t foot = 0;
+};
+
+struct Slot {
+  std::thread worker;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  std::unique_ptr<Request> job;  // assigned request (null when idle)
+  std::condition_variable cv;
+};
+
+}  // namespace
+
+struct helm_server {
+  size_t budget = 0;
+  double max_bypass = 0.0;
+  helm_opts opts{};
+  int device = 0;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_done;
+  std::deque<std::unique_ptr<Request>> queue;
+  std::vector<std::unique_ptr<Slot>> slots;
+  std::deque<helm_request_record> done;
+  size_t used = 0;
+  long long submitted = 0, completed = 0;
+  bool stop = false;
+  std::mutex plan_mu;
+  std::map<std::string, helm_plan*> plans;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  // Admit as many queued requests as the policy allows (called with mu held).
+  void admit_locked() {
+    for (;;) {
+      int free_slots = 0;
+      for (auto& s : slots)
+        if (!s->job) ++free_slots;
+      struct View {
+        const std::deque<std::unique_ptr<Request>>& q;
+        bool empty() const { return q.empty(); }
+        size_t size() const { return q.size(); }
+        Pending operator[](size_t i) const { return {q[i]->t_submit, q[i]->foot}; }
+        Pending front() const { return (*this)[0]; }
+      } view{queue};
+      const int i = pick_next(view, free_slots, used, budget, now(), max_bypass);
+      if (i < 0) return;
+      std::unique_ptr<Request> r = std::move(queue[i]);
+      queue.erase(queue.begin() + i);
+      r->t_admit = now();
+      used += r->foot;
+      for (auto& s : slots)
+        if (!s->job) {
+          s->job = std::move(r);
+          s->cv.notify_one();
+          break;
+        }
+    }
+  }
+
+  void work(int k) {
+    (void)hipSetDevice(device);
+    Slot& s = *slots[k];
+    for (;;) {
+      std::unique_ptr<Request>* jp = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        s.cv.wait(lk, [&] { return stop || s.job != nullptr; });
+        if (!s.job) return;  // stop requested and idle
+        jp = &s.job;
+      }
+      Request& r = **jp;
+      helm_info info{};
+      helm_status st = HELM_OK;
+      if (s.ws_cap < r.foot) {
+        if (s.ws) (void)hipFree(s.ws);
+        s.ws = nullptr;
+        s.ws_cap = 0;
+        if (hipMalloc(&s.ws, r.foot) == hipSuccess)
+          s.ws_cap = r.foot;
+        else
+          st = HELM_ENOMEM;
+      }
+      if (st == HELM_OK) st = helm_solve(r.plan, r.f, r.u, r.nrhs, r.sigma.data(), s.ws, s.stream, &info);
+      if (st == HELM_OK && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
+      helm_request_record rec{};
+      rec.id = r.id;
+      rec.status = st;
+      rec.sweeps = info.sweeps;
+      rec.last_correction = info.last_correction;
+      rec.t_submit = r.t_submit;
+      rec.t_admit = r.t_admit;
+      rec.t_done = now();
+      rec.footprint = r.foot;
+      rec.slot = k;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        used -= r.foot;
+        s.job.reset();
+        done.push_back(rec);
+        ++completed;
+        admit_locked();
+      }
+      cv_done.notify_all();
+    }
+  }
+};
+
+namespace {
+std::string plan_key(const helm_grid* g, const helm_bc* bc) {
+  std::string k;
+  for (int d = 0; d < 3; ++d) {
+    k.append(reinterpret_cast<const char*>(&g->n[d]), sizeof(int));
+    k.append(reinterpret_cast<const char*>(g->faces[d]), sizeof(double) * (g->n[d] + 1));
+    k.push_back(static_cast<char>(g->loc[d]));
+    k.push_back(static_cast<char>(bc->lo[d]));
+    k.push_back(static_cast<char>(bc->hi[d]));
+  }
+  return k;
+}
+}  // namespace
+
+extern "C" helm_status helm_server_create(size_t hbm_budget_bytes, int slots, double max_bypass_ms,
+                                          const helm_opts* opts, helm_server** out) {
+  if (!out || slots < 1 || slots > 16 || hbm_budget_bytes == 0 || !(max_bypass_ms >= 0.0)) return HELM_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<helm_server> s(new (std::nothrow) helm_server());
+  if (!s) return HELM_ENOMEM;
+  s->budget = hbm_budget_bytes;
+  s->max_bypass = max_bypass_ms * 1e-3;
+  helm_default_opts(&s->opts);
+  if (opts) s->opts = *opts;
+  if (hipGetDevice(&s->device) != hipSuccess) return HELM_EDEVICE;
+  s->t0 = std::chrono::steady_clock::now();
+  for (int k = 0; k < slots; ++k) {
+    auto sl = std::make_unique<Slot>();
+    if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) return HELM_EDEVICE;
+    s->slots.push_back(std::move(sl));
+  }
+  helm_server* raw = s.get();
+  for (int k = 0; k < slots; ++k) raw->slots[k]->worker = std::thread([raw, k] { raw->work(k); });
+  *out = s.release();
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_server_submit(helm_server* s, const helm_grid* grid, const helm_bc* bc, const double* sigma,
+                                          int nrhs, const double* f, double* u, long long id) {
+  if (!s || !grid || !bc || !sigma || !f || !u || nrhs < 1 || nrhs > 64) return HELM_EINVAL;
+  const double t_submit = s->now();
+  helm_plan* plan = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->plan_mu);
+    const std::string key = plan_key(grid, bc);
+    auto it = s->plans.find(key);
+    if (it != s->plans.end()) {
+      plan = it->second;
+    } else {
+      const helm_status st = helm_setup(grid, bc, 0.0, &s->opts, &plan);
+      if (st != HELM_OK) return st;
+      s->plans[key] = plan;
+    }
+  }
+  auto r = std::make_unique<Request>();
+  r->id = id;
+  r->plan = plan;
+  r->sigma.assign(sigma, sigma + nrhs);
+  r->nrhs = nrhs;
+  r->f = f;
+  r->u = u;
+  r->t_submit = t_submit;
+  helm_status st = helm_workspace_size(plan, nrhs, &r->foot);
+  if (st != HELM_OK) return st;
+  if (r->foot > s->budget) return HELM_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->queue.push_back(std::move(r));
+    ++s->submitted;
+    s->admit_locked();
+  }
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_server_poll(helm_server* s, helm_request_record* out, int max, int* n, int wait_ms) {
+  if (!s || !n || (max > 0 && !out)) return HELM_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_ms > 0)
+    s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !s->done.empty(); });
+  int k = 0;
+  while (k < max && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n = k;
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_server_drain(helm_server* s) {
+  if (!s) return HELM_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->completed == s->submitted; });
+  return HELM_OK;
+}
+
+extern "C" double helm_server_now(const helm_server* s) { return s ? s->now() : 0.0; }
+
+extern "C" void helm_server_destroy(helm_server* s) {
+  if (!s) return;
+  helm_server_drain(s);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  for (auto& sl : s->slots) sl->cv.notify_all();
+  for (auto& sl : s->slots) {
+    if (sl->worker.joinable()) sl->worker.join();
+    if (sl->ws) (void)hipFree(sl->ws);
+    if (sl->stream) (void)hipStreamDestroy(sl->stream);
+  }
+  for (auto& kv : s->plans) helm_destroy(kv.second);
+  delete s;
+}
+
+// ---------------------------------------------------------------- virtual-clock simulation
+extern "C" helm_status helm_sched_simulate(int n, const double* arrival, const double* service, const size_t* foot,
+                                           int slots, size_t budget, double max_bypass_ms, double* admit,
+                                           double* done) {
+  if (n < 0 || slots < 1 || (n > 0 && (!arrival || !service || !foot || !admit || !done))) return HELM_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (foot[i] > budget || !(service[i] >= 0.0)) return HELM_EINVAL;
+    if (i > 0 && arrival[i] < arrival[i - 1]) return HELM_EINVAL;
+  }
+  const double max_bypass = max_bypass_ms * 1e-3;
+  struct Q {
+    std::deque<int> idx;
+    const double* arr;
+    const size_t* ft;
+    bool empty() const { return idx.empty(); }
+    size_t size() const { return idx.size(); }
+    Pending operator[](size_t i) const { return {arr[idx[i]], ft[idx[i]]}; }
+    Pending front() const { return (*this)[0]; }
+  } q{{}, arrival, foot};
+  std::vector<std::pair<double, int>> running;  // (finish time, request)
+  size_t used = 0;
+  int next = 0, finished = 0;
+  double now = 0.0;
+  while (finished < n) {
+    // next event: an arrival or the earliest completion
+    double t_arr = next < n ? arrival[next] : 1e300;
+    double t_fin = 1e300;
+    for (auto& r : running) t_fin = std::min(t_fin, r.first);
+    now = std::min(t_arr, t_fin);
+    // completions at `now`
+    for (size_t i = 0; i < running.size();) {
+      if (running[i].first <= now) {
+        used -= foot[running[i].second];
+        ++finished;
+        running.erase(running.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+    while (next < n && arrival[next] <= now) q.idx.push_back(next++);
+    for (;;) {
+      const int i = pick_next(q, slots - static_cast<int>(running.size()), used, budget, now, max_bypass);
+      if (i < 0) break;
+      const int r = q.idx[i];
+      q.idx.erase(q.idx.begin() + i);
+      admit[r] = now;
+      done[r] = now + service[r];
+      used += foot[r];
+      running.push_back({done[r], r});
+    }
+  }
+  return HELM_OK;
+}

@@ -1,0 +1,126 @@
+"""GPU tests of the continuous-batching server.
+
+Each request's result in the mix must equal the same request solved alone (the same kernels
+on the same data: bitwise equality is expected, and at worst the solver tolerance); the
+device-workspace budget is respected at every instant; requests overlap in time when the
+budget and slots allow it, and are serialised when the budget admits only one at a time.
+"""
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = ((24, 20, 28), (32, 32, 32), (40, 24, 16), (17, 33, 21))
+BIG_GRIDS = ((64, 64, 64), (96, 64, 80), (128, 128, 128))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1107_2461_amd import load
+    load()
+    return t
+
+
+def _requests(torch, n, seed, grids=GRIDS):
+    reqs = workloads.serving_requests(seed, n, rate_hz=1000.0, grids=grids)
+    out = []
+    for r in reqs:
+        prob = workloads.serving_problem(r)
+        g = torch.Generator(device="cuda").manual_seed(r["rhs_seed"])
+        nx, ny, nz = prob.shape_xyz
+        f = torch.randn((r["nrhs"], nz, ny, nx), generator=g, device="cuda", dtype=torch.float64)
+        out.append((r, prob, f))
+    return out
+
+
+def _run_server(torch, reqs, precision, budget, slots, warm=True):
+    """Submit every request back to back (after a first pass that fills the plan cache)."""
+    from paper_1107_2461_amd import Server
+    srv = Server(budget, slots=slots, precision=precision, max_bypass_ms=20.0)
+    outs, recs = {}, []
+    for _ in range(2 if warm else 1):
+        outs = {}
+        for r, prob, f in reqs:
+            u = torch.empty_like(f)
+            outs[r["rid"]] = u
+            srv.submit(r["rid"], prob.faces, f, u, [prob.sigma] * f.shape[0], prob.bc_lo, prob.bc_hi)
+        srv.drain()
+        recs = srv.poll(max_records=len(reqs) + 8)
+    srv.close()
+    torch.cuda.synchronize()
+    return outs, recs
+
+
+def _alone(torch, prob, f, precision):
+    from paper_1107_2461_amd import Plan
+    plan = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, precision=precision)
+    u = plan.solve(f)
+    torch.cuda.synchronize()
+    return u
+
+
+def _same(torch, a, b):
+    return torch.equal(a, b) or float((a - b).norm() / a.norm()) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3_ir"])
+def test_mix_equals_alone_and_overlaps(torch, precision):
+    budget = 2 << 30
+    reqs = _requests(torch, 24, seed=5, grids=BIG_GRIDS)
+    outs, recs = _run_server(torch, reqs, precision, budget=budget, slots=4)
+    assert len(recs) == len(reqs)
+    assert all(r["status"] == 0 for r in recs), recs
+    bitwise = 0
+    for r, prob, f in reqs:
+        ua = _alone(torch, prob, f, precision)
+        um = outs[r["rid"]]
+        bitwise += int(torch.equal(ua, um))
+        assert _same(torch, ua, um), r
+    print(f"{precision}: {bitwise}/{len(reqs)} results bitwise identical alone and in the mix")
+    # budget and slots respected at every admission instant; some requests ran concurrently
+    for t in sorted({x["t_admit"] for x in recs}):
+        live = [x for x in recs if x["t_admit"] <= t < x["t_done"]]
+        assert sum(x["footprint"] for x in live) <= budget
+        assert len(live) <= 4
+    overl = sum(1 for a in recs for b in recs
+                if a["id"] < b["id"] and a["t_admit"] < b["t_done"] and b["t_admit"] < a["t_done"])
+    print(f"{precision}: {overl} overlapping request pairs")
+    assert overl > 0
+    for x in recs:
+        assert x["t_submit"] <= x["t_admit"] <= x["t_done"]
+    # cold plans, ragged grids, mixed walls, Laplace requests
+    small = _requests(torch, 16, seed=7)
+    outs_s, _ = _run_server(torch, small, precision, budget=64 << 20, slots=4, warm=False)
+    for r, prob, f in small:
+        assert _same(torch, _alone(torch, prob, f, precision), outs_s[r["rid"]]), r
+
+
+def test_tight_budget_serialises(torch):
+    from paper_1107_2461_amd import Plan
+    reqs = _requests(torch, 8, seed=6, grids=BIG_GRIDS)
+    foot = 0
+    for r, prob, f in reqs:
+        p = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma)
+        foot = max(foot, p.workspace_bytes(f.shape[0]))
+    outs, recs = _run_server(torch, reqs, "fp64", budget=foot, slots=4)
+    for a in recs:
+        for b in recs:
+            if a["id"] < b["id"] and a["footprint"] + b["footprint"] > foot:
+                # two requests that do not fit together never run at the same time
+                assert a["t_done"] <= b["t_admit"] + 1e-9 or b["t_done"] <= a["t_admit"] + 1e-9
+    for r, prob, f in reqs:
+        assert _same(torch, _alone(torch, prob, f, "fp64"), outs[r["rid"]])
+
+
+def test_submit_rejects_request_larger_than_budget(torch):
+    from paper_1107_2461_amd import HelmError, Server
+    prob = workloads.box_problem(32, 1.5, 1.0)
+    f = torch.zeros((1, 32, 32, 32), dtype=torch.float64, device="cuda")
+    srv = Server(1024, slots=1)
+    with pytest.raises(HelmError, match="EINVAL"):
+        srv.submit(1, prob.faces, f, torch.empty_like(f), [1.0])
+    srv.close()
