@@ -176,6 +176,38 @@ def cpu_baseline(prob, f, golden, budget_s):
                 seconds_per_solve=t_solve)
 
 
+KERNEL_SOURCES = {
+    # stage family -> sources whose change invalidates a committed traffic measurement
+    "bf16x3": ["paper_1107_2461_amd/csrc/rot_bf16x3.hpp", "paper_1107_2461_amd/csrc/modes_bf16x3.hip",
+               "paper_1107_2461_amd/csrc/mode_common.hpp"],
+    "fp64": ["paper_1107_2461_amd/csrc/mode_common.hpp", "paper_1107_2461_amd/csrc/modes_f64.hip"],
+}
+
+
+def source_hash(prec):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES.get(prec, []):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(prec, stage):
+    """HBM bytes per launch of a stage from profiles/traffic.json, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = data.get(prec, {}).get(stage)
+    if not ent or ent.get("source_hash") != source_hash(prec):
+        return None
+    return ent.get("bytes_per_launch")
+
+
 def run_serving(torch, args):
     """Serving stream: Poisson arrivals of mixed solve requests through the continuous-batching server."""
     from paper_1107_2461_amd import Server
@@ -254,6 +286,8 @@ def main():
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (a reference dispatch for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=300)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -282,6 +316,14 @@ def main():
             golden = json.load(open(gp))
     nrhs = f.shape[0]
     f_dev = torch.from_numpy(f).to("cuda")
+    if args.copy_ref_mb:
+        src = torch.ones(args.copy_ref_mb << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] reference copy: {args.copy_ref_mb} MiB read + {args.copy_ref_mb} MiB written")
+        del src, dst
     results = {}
     for path in args.paths.split(","):
         log(f"[bench] path {path} ...")
@@ -296,7 +338,8 @@ def main():
               key=lambda s: b["stages"][s]["total_ms_per_step"])
     d = b["stages"][dom]
     roofline = dict(kernel=dom, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
-                    frac=d["frac"], traffic=None, avg_us=d["avg_us"])
+                    frac=d["frac"], traffic=committed_traffic(b["precision"], dom), avg_us=d["avg_us"],
+                    algorithmic_bytes=d.get("algorithmic_bytes"), algorithmic_flops=d.get("algorithmic_flops"))
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
