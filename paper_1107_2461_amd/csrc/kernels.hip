@@ -59,8 +59,8 @@ void swizzle_operand(Prec p, int K, const double* M, void* out) {
         }
 }
 
-hipError_t mode_rot_bf16x3(int, const void*, long long, int, const float*, void*, long long, long long, Epi, bool,
-                           const EpiArgs&, hipStream_t);
+hipError_t mode_rot_bf16x3(int, const void*, long long, int, const void*, bool, void*, long long, long long, Epi,
+                           bool, const EpiArgs&, hipStream_t);
 
 size_t swizzled_bf16x3_bytes(int K) { return 3 * swizzled_bytes(P_BF16, K); }
 
@@ -78,16 +78,16 @@ void swizzle_bf16x3(int K, const double* M, void* out) {
   }
 }
 
-hipError_t mode_rot(const void* Msw, int K, const float* X, void* Y, long long R, long long PQ, Epi epi,
+hipError_t mode_rot(const void* Msw, int K, const void* X, bool x_f64, void* Y, long long R, long long PQ, Epi epi,
                     const EpiArgs& ep, hipStream_t st) {
   const int ci = choose_cfg(K);
   if (ci < 0 || K < 1 || R < 1 || PQ < 1 || R > kMaxRhs) return hipErrorInvalidValue;
   if ((R * PQ + 15) / 16 > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (epi == EPI_ACCUM && (ep.norms == nullptr)) return hipErrorInvalidValue;
-  const bool vec = (K % 8 == 0) && (PQ % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 32 == 0) &&
+  if (epi == EPI_ACCUM) return hipErrorInvalidValue;  // refinement updates use update_u
+  const bool vec = (K % 8 == 0) && (PQ % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 64 == 0) &&
                    (reinterpret_cast<uintptr_t>(Y) % 32 == 0);
   const long long piece = static_cast<long long>(swizzled_bytes(P_BF16, K) / 2);
-  return mode_rot_bf16x3(ci, Msw, piece, K, X, Y, R, PQ, epi, vec, ep, st);
+  return mode_rot_bf16x3(ci, Msw, piece, K, X, x_f64, Y, R, PQ, epi, vec, ep, st);
 }
 
 hipError_t mode_left(Prec p, const void* Msw, int K, const void* X, Prec tin, void* Y, Prec tout, long long S,
@@ -249,39 +249,92 @@ hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const d
 // A block of 64 x 4 lanes owns a 64 x 4 patch of (x, y) lines and marches along z through a
 // chunk of planes, carrying u(k-1), u(k), u(k+1) in registers, so u and f stream through
 // once; x and y neighbours come from the lanes next door (L1) or the adjacent patch (L2).
-template <typename TOut>
-__global__ __launch_bounds__(256) void k_stencil(int mode, const double* __restrict__ u,
+// Column segments: a lane owns one x index and kStencilJS consecutive y rows and marches up a
+// z-chunk, keeping the rows of planes k-1, k (with the two y-halo rows) and k+1 in registers.
+// The x neighbours come from the adjacent lanes (cross-lane shuffle); only the two edge lanes
+// of a wave load one value each.  A workgroup is 4 waves: wx of them side by side in x (64 x
+// indices each) times 4 / wx row segments.  Workgroups are numbered so that each XCD (which
+// receives every 8th workgroup) walks a contiguous range of tiles, y fastest then z: the halo
+// rows and planes a tile shares with its neighbours are then read while they sit in that
+// XCD's L2.  Per point: 8 B of u, 8 B of f in, one value out, plus halo re-reads.
+constexpr int kStencilJS = 4;
+
+__device__ inline double lane_below(double v, int lane) { return __shfl(v, lane > 0 ? lane - 1 : 0); }
+__device__ inline double lane_above(double v, int lane) { return __shfl(v, lane < 63 ? lane + 1 : 63); }
+
+template <typename TOut, int MODE>  // MODE 0: out = H u, 1: out = f - H u
+__global__ __launch_bounds__(256) void k_stencil(const double* __restrict__ u,
                                                  const double* __restrict__ f, TOut* __restrict__ out,
-                                                 StencilArgs a, int zchunk, int nzc) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int zc = blockIdx.z % nzc;
-  const int r = blockIdx.z / nzc;
-  if (i >= a.nx || j >= a.ny) return;
+                                                 StencilArgs a, int zchunk, int nzc, int wx, int nbx, int nby) {
+  constexpr int JS = kStencilJS;
+  // the wave index is uniform: the row segment (and its coefficients) then live in SGPRs
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nt = gridDim.x;
+  const int per = nt / 8;
+  int t = blockIdx.x;
+  if (per > 0 && t < per * 8) t = (t % 8) * per + t / 8;
+  const int bxx = t % nbx;
+  t /= nbx;
+  const int byy = t % nby;
+  t /= nby;
+  const int zc = t % nzc;
+  const int r = t / nzc;
+  const int i = (bxx * wx + w % wx) * 64 + lane;
+  const int j0 = (byy * (4 / wx) + w / wx) * JS;
   const int k0 = zc * zchunk;
   const int k1 = min(a.nz, k0 + zchunk);
-  if (k0 >= k1) return;
+  if (k0 >= k1 || j0 >= a.ny) return;
+  const bool iok = i < a.nx;
+  const int ic = iok ? i : a.nx - 1;  // lanes past the end load a valid column, store nothing
   const long long plane = static_cast<long long>(a.nx) * a.ny;
-  const long long off = static_cast<long long>(r) * plane * a.nz + static_cast<long long>(j) * a.nx + i;
-  const double* ur = u + off;
-  const double cxl = a.cx[3 * i], cxd = a.cx[3 * i + 1], cxu = a.cx[3 * i + 2];
-  const double cyl = a.cy[3 * j], cyd = a.cy[3 * j + 1], cyu = a.cy[3 * j + 2];
-  const double diag_xy = a.sigma[r] + cxd + cyd;
-  const bool hx_lo = i > 0, hx_hi = i + 1 < a.nx, hy_lo = j > 0, hy_hi = j + 1 < a.ny;
-  double u_dn = k0 > 0 ? ur[(k0 - 1) * plane] : 0.0;
-  double u_c = ur[k0 * plane];
+  const long long rbase = static_cast<long long>(r) * plane * a.nz;
+  const double cxl = a.cx[3 * ic], cxd = a.cx[3 * ic + 1], cxu = a.cx[3 * ic + 2];
+  const bool hx_lo = ic > 0, hx_hi = ic + 1 < a.nx;
+  int jr[JS + 2];  // rows j0-1 .. j0+JS, clamped into the grid
+#pragma unroll
+  for (int s = 0; s < JS + 2; ++s) jr[s] = min(max(j0 - 1 + s, 0), a.ny - 1);
+  double cyl[JS], cyu[JS], dxy[JS];
+#pragma unroll
+  for (int s = 0; s < JS; ++s) {
+    const int j = jr[s + 1];
+    cyl[s] = (j0 + s > 0 && j0 + s < a.ny) ? a.cy[3 * j] : 0.0;
+    cyu[s] = (j0 + s + 1 < a.ny) ? a.cy[3 * j + 2] : 0.0;
+    dxy[s] = a.sigma[r] + cxd + a.cy[3 * j + 1];
+  }
+  const double* ucol = u + rbase + ic;
+  auto at = [&](int k, int s) { return ucol + k * plane + static_cast<long long>(jr[s]) * a.nx; };
+  double um[JS], uc[JS + 2], up[JS + 2];
+#pragma unroll
+  for (int s = 0; s < JS; ++s) um[s] = k0 > 0 ? *at(k0 - 1, s + 1) : 0.0;
+#pragma unroll
+  for (int s = 0; s < JS + 2; ++s) uc[s] = *at(k0, s);
   for (int k = k0; k < k1; ++k) {
-    const long long q = k * plane;
-    const double u_up = (k + 1 < a.nz) ? ur[q + plane] : 0.0;
-    double h = (diag_xy + a.cz[3 * k + 1]) * u_c + a.cz[3 * k] * u_dn + a.cz[3 * k + 2] * u_up;
-    if (hx_lo) h += cxl * ur[q - 1];
-    if (hx_hi) h += cxu * ur[q + 1];
-    if (hy_lo) h += cyl * ur[q - a.nx];
-    if (hy_hi) h += cyu * ur[q + a.nx];
-    const double res = mode == 1 ? f[off + q] - h : h;
-    out[off + q] = store_cvt<TOut>(res);
-    u_dn = u_c;
-    u_c = u_up;
+    double xs[JS], fv[JS];
+    // x neighbours and f of plane k first, plane k+1 (next step's centre) last
+#pragma unroll
+    for (int s = 0; s < JS; ++s) {
+      double lo = lane_below(uc[s + 1], lane), hi = lane_above(uc[s + 1], lane);
+      const double* p = at(k, s + 1);
+      if (lane == 0 && hx_lo) lo = p[-1];
+      if (lane == 63 && hx_hi) hi = p[1];
+      xs[s] = (hx_lo ? cxl * lo : 0.0) + (hx_hi ? cxu * hi : 0.0);
+      fv[s] = MODE == 1 ? f[rbase + k * plane + static_cast<long long>(jr[s + 1]) * a.nx + ic] : 0.0;
+    }
+    const bool has_up = k + 1 < a.nz;
+#pragma unroll
+    for (int s = 0; s < JS + 2; ++s) up[s] = has_up ? *at(k + 1, s) : 0.0;
+    const double czl = a.cz[3 * k], czd = a.cz[3 * k + 1], czu = a.cz[3 * k + 2];
+#pragma unroll
+    for (int s = 0; s < JS; ++s) {
+      const double h = (dxy[s] + czd) * uc[s + 1] + czl * um[s] + czu * up[s + 1] + cyl[s] * uc[s] +
+                       cyu[s] * uc[s + 2] + xs[s];
+      const double res = MODE == 1 ? fv[s] - h : h;
+      if (iok && j0 + s < a.ny) out[rbase + k * plane + static_cast<long long>(j0 + s) * a.nx + i] = store_cvt<TOut>(res);
+    }
+#pragma unroll
+    for (int s = 0; s < JS; ++s) um[s] = uc[s + 1];
+#pragma unroll
+    for (int s = 0; s < JS + 2; ++s) uc[s] = up[s];
   }
 }
 
@@ -305,19 +358,32 @@ hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec t
       hipLaunchKernelGGL(k_convert<bf16_t>, grid, block, 0, st, f, static_cast<bf16_t*>(out), n);
     return hipGetLastError();
   }
-  const int bx = (a.nx + 63) / 64, by = (a.ny + 3) / 4;
-  const long long xy_blocks = static_cast<long long>(bx) * by * a.nrhs;
-  int nzc = static_cast<int>(std::max<long long>(1, std::min<long long>(a.nz, (2048 + xy_blocks - 1) / xy_blocks)));
+  // waves side by side in x: 4 for nx > 128, 2 for nx > 64, else 1 (the rest stack in y)
+  const int wx = a.nx > 128 ? 4 : (a.nx > 64 ? 2 : 1);
+  const int nbx = (a.nx + 64 * wx - 1) / (64 * wx);
+  const int rows = (4 / wx) * kStencilJS;  // y rows per workgroup
+  const int nby = (a.ny + rows - 1) / rows;
+  const long long xy_blocks = static_cast<long long>(nbx) * nby * a.nrhs;
+  // z-chunks: enough workgroups to fill the chip (about 2048), chunks of at least 4 planes
+  int nzc = static_cast<int>(std::max<long long>(1, std::min<long long>((a.nz + 3) / 4, (2048 + xy_blocks - 1) / xy_blocks)));
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
-  const dim3 grid(bx, by, nzc * a.nrhs), block(64, 4);
+  const long long tiles = xy_blocks * nzc;
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(tiles)), block(256);
+  auto launch = [&](auto out_type, auto mode_c) {
+    using TOut = decltype(out_type);
+    hipLaunchKernelGGL((k_stencil<TOut, decltype(mode_c)::value>), grid, block, 0, st, u, f, static_cast<TOut*>(out),
+                       a, zchunk, nzc, wx, nbx, nby);
+  };
+  using M0 = std::integral_constant<int, 0>;
+  using M1 = std::integral_constant<int, 1>;
   if (tout == P_F64)
-    hipLaunchKernelGGL(k_stencil<double>, grid, block, 0, st, mode, u, f, static_cast<double*>(out), a, zchunk, nzc);
+    mode == 1 ? launch(double{}, M1{}) : launch(double{}, M0{});
   else if (tout == P_F32)
-    hipLaunchKernelGGL(k_stencil<float>, grid, block, 0, st, mode, u, f, static_cast<float*>(out), a, zchunk, nzc);
+    mode == 1 ? launch(float{}, M1{}) : launch(float{}, M0{});
   else
-    hipLaunchKernelGGL(k_stencil<bf16_t>, grid, block, 0, st, mode, u, f, static_cast<bf16_t*>(out), a, zchunk,
-                       nzc);
+    mode == 1 ? launch(bf16_t{}, M1{}) : launch(bf16_t{}, M0{});
   return hipGetLastError();
 }
 

@@ -15,7 +15,8 @@ enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 /* split BF16, 
 enum Epi : int {
   EPI_STORE = 0,   // Y = acc (converted to the output storage type)
   EPI_DIVIDE = 1,  // Y = acc / (lam_x[a] + lam_y[b] + lam_z[c] + sigma[r]) in FP64 (eqs. 26-28)
-  EPI_ACCUM = 2    // u += acc in FP64, with per-RHS max|acc| and max|u| (refinement update)
+  EPI_ACCUM = 2,   // u += acc in FP64, with per-RHS max|acc| and max|u| (refinement update)
+  EPI_STORE_F64 = 3  // Y = acc widened to FP64 (split-BF16 products: first solve writes u directly)
 };
 
 constexpr int kMaxRhs = 64;
@@ -28,6 +29,7 @@ struct EpiArgs {
   const double* lamx = nullptr;   // eigenvalues of the x and y axes (divide epilogue)
   const double* lamy = nullptr;
   const double* lamz = nullptr;   // eigenvalues of the contracted (z) axis
+  const double* lamxy = nullptr;  // lamx[a] + lamy[b] at pq = b * nx + a (split-BF16 divide)
   int nx = 1;                     // x extent, to split a column index into (b, a)
   int eq28 = 0;                   // zero denominator -> 1 (eq. 28) instead of projection
   unsigned long long* norms = nullptr;  // [2 * nrhs * kNormStripes] (accumulate), see kNormStripes
@@ -55,11 +57,12 @@ hipError_t mode_right(Prec p, const void* Msw, int K, const void* X, Prec tin, v
 // Split-BF16 rotating-layout product (three bfloat16 pieces, six MFMA partial products,
 // FP32 accumulation and storage):  Y[r][a][pq] = sum_k M[a][k] X[r][pq][k],
 // r < R, pq < PQ, a < K.  Msw holds the three swizzled pieces of M, `piece` elements apart.
-// epi: STORE (FP32 Y), DIVIDE (FP32 Y, pq = b * nx + a_x, column a = the z index c) or
-// ACCUM (FP64 Y += result, with per-RHS norms).
+// epi: STORE (FP32 Y), DIVIDE (FP32 Y, pq = b * nx + a_x, column a = the z index c, FP32
+// divide by the FP64-summed eigenvalues, ep.lamxy required) or STORE_F64 (FP64 Y).
 size_t swizzled_bf16x3_bytes(int K);
 void swizzle_bf16x3(int K, const double* M, void* out);
-hipError_t mode_rot(const void* Msw, int K, const float* X, void* Y, long long R, long long PQ, Epi epi,
+// x_f64: X is FP64 (the solve's right-hand side, rounded to FP32 on load), else FP32.
+hipError_t mode_rot(const void* Msw, int K, const void* X, bool x_f64, void* Y, long long R, long long PQ, Epi epi,
                     const EpiArgs& ep, hipStream_t st);
 
 // Batched Thomas solve along z (TPT, end of Section 3): for every RHS r and (b, a) line,

@@ -123,10 +123,12 @@ __device__ inline double recip(double d) {
   e = fma(-d, r, 1.0);
   return fma(r, e, r);
 }
-__device__ inline double divide_by_eigs(double v, const EpiArgs& ep, int c, double shift) {
-  const double den = ep.lamz[c] + shift;
+__device__ inline double divide_den(double v, const EpiArgs& ep, double den) {
   if (den == 0.0) return ep.eq28 ? v : 0.0;
   return v * recip(den);
+}
+__device__ inline double divide_by_eigs(double v, const EpiArgs& ep, int c, double shift) {
+  return divide_den(v, ep, ep.lamz[c] + shift);
 }
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -253,6 +255,20 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
         for (int s = 0; s < 4; ++s) b_cur[nb][s] = b_nxt[nb][s];
     }
   }
+  // eigenvalues of the lane's rows, all loaded before the first store (the vector-memory
+  // counter also counts stores: a load issued after a store would wait for it); the widest
+  // entry (NB = 8, K <= 32) has no registers to spare and loads them at the store
+  constexpr bool kPre = EPI == EPI_DIVIDE && NB <= 4;
+  [[maybe_unused]] double lz[kPre ? MB : 1][4];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = (rb0 + mb) * 16 + T::row(g, r);
+        lz[mb][r] = a < K ? ep.lamz[a] : 1.0;
+      }
+  }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -263,7 +279,8 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
         if (a >= K || !colok[nb]) continue;
         const long long idx = base[nb] + static_cast<long long>(a) * Nn;
         if constexpr (EPI == EPI_DIVIDE) {
-          Y[idx] = store_cvt<TC>(divide_by_eigs(static_cast<double>(acc[mb][nb][r]), ep, a, den_xy[nb]));
+          const double lza = kPre ? lz[kPre ? mb : 0][r] : ep.lamz[a];
+          Y[idx] = store_cvt<TC>(divide_den(static_cast<double>(acc[mb][nb][r]), ep, lza + den_xy[nb]));
         } else {
           Y[idx] = static_cast<TC>(acc[mb][nb][r]);
         }

@@ -30,6 +30,7 @@ namespace helm {
 
 typedef float f8v __attribute__((ext_vector_type(8)));
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d8v __attribute__((ext_vector_type(8)));
 
 __device__ inline unsigned short bf16_bits(float x) {
   return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));  // v_cvt_pk_bf16_f32 (RNE)
@@ -50,9 +51,11 @@ __device__ inline void split3(const f8v& x, u16x8& hi, u16x8& mid, u16x8& lo) {
   }
 }
 
-template <int W, int NB, int MB, int EPI, bool VEC>
+// TIn: float for intermediates, double when the first product reads the FP64 right-hand side
+// directly (rounded to FP32 on load, as a separate conversion pass would).
+template <int W, int NB, int MB, int EPI, bool VEC, typename TIn = float>
 __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict__ Msw, long long piece, int KB, int K,
-                                                       const float* __restrict__ X, void* __restrict__ Yv,
+                                                       const TIn* __restrict__ X, void* __restrict__ Yv,
                                                        long long R, long long PQ, EpiArgs ep) {
   constexpr int WM = 4 / W;
   constexpr int MT = WM * MB * 16;        // rows per workgroup
@@ -62,7 +65,8 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   __shared__ u16x8 lds[2][3][RB * 64];    // [buffer][piece][row block * 64 + lane]
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform: keep it (and every B-fragment base address) in scalar registers
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wn = wave % W, wm = wave / W;
   const int l16 = lane & 15, g = lane >> 4;
   const long long Mrows = R * PQ;
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   const int rb0 = wm * MB;                // this wave's first row block inside the tile
 
   // producer assignment: chunk c -> row block c / 64, fragment lane c % 64
-  const float* src[CPT];
+  const TIn* src[CPT];
   bool srcok[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
@@ -81,30 +85,36 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
     srcok[q] = c < CHUNKS && row < Mrows;
     src[q] = X + (srcok[q] ? row : 0) * K + 8 * (ln >> 4);
   }
-  auto load_tile = [&](int kb, f8v (&v)[CPT]) {
+  // tiles are staged raw (FP32, or FP64 for the first product of a solve) and rounded to
+  // FP32 when split, so a wait for a staged load never precedes the MFMA work it overlaps
+  using raw_t = typename std::conditional<sizeof(TIn) == 8, d8v, f8v>::type;
+  auto load_tile = [&](int kb, raw_t (&v)[CPT]) {
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int kq = kb * 32 + 8 * (((tid + q * 256) & 63) >> 4);
       if constexpr (VEC) {
         if (srcok[q] && kq < K) {
-          v[q] = *reinterpret_cast<const f8v*>(src[q] + kb * 32);
+          v[q] = *reinterpret_cast<const raw_t*>(src[q] + kb * 32);
         } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[q][j] = 0.f;
+          for (int j = 0; j < 8; ++j) v[q][j] = 0;
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[q][j] = (srcok[q] && kq + j < K) ? src[q][kb * 32 + j] : 0.f;
+        for (int j = 0; j < 8; ++j) v[q][j] = (srcok[q] && kq + j < K) ? src[q][kb * 32 + j] : TIn(0);
       }
     }
   };
-  auto store_tile = [&](int buf, const f8v (&v)[CPT]) {
+  auto store_tile = [&](int buf, const raw_t (&v)[CPT]) {
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int c = tid + q * 256;
       if (c < CHUNKS) {
+        f8v x;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = static_cast<float>(v[q][j]);
         u16x8 h, m, l;
-        split3(v[q], h, m, l);
+        split3(x, h, m, l);
         lds[buf][0][c] = h;
         lds[buf][1][c] = m;
         lds[buf][2][c] = l;
@@ -118,20 +128,22 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
 
-  // B fragments (the three pieces of M) of one k-block for this wave's NB column blocks
+  // B fragments (the three pieces of M) of one k-block for this wave's NB column blocks:
+  // wave-uniform base + 32-bit lane offset (scalar-base addressing, one VGPR)
+  const unsigned lane_off = static_cast<unsigned>(lane) * 8u;
   auto load_b = [&](int kb, u16x8 (&b)[NB][3]) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const long long o = ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 8;
-      b[nb][0] = *reinterpret_cast<const u16x8*>(Msw + o);
-      b[nb][1] = *reinterpret_cast<const u16x8*>(Msw + piece + o);
-      b[nb][2] = *reinterpret_cast<const u16x8*>(Msw + 2 * piece + o);
+      const bf16_t* base = Msw + (static_cast<long long>(cb0 + nb) * KB + kb) * 512;
+      b[nb][0] = *reinterpret_cast<const u16x8*>(base + lane_off);
+      b[nb][1] = *reinterpret_cast<const u16x8*>(base + piece + lane_off);
+      b[nb][2] = *reinterpret_cast<const u16x8*>(base + 2 * piece + lane_off);
     }
   };
   // input tiles kb+1 .. kb+DEPTH are in flight in registers while k-block kb is multiplied,
   // so the HBM latency is covered by DEPTH k-blocks of MFMA work
-  constexpr int DEPTH = 2;
-  f8v stage[DEPTH][CPT];
+  constexpr int DEPTH = sizeof(TIn) == 8 ? 1 : 2;  // FP64 staging: twice the registers per tile
+  raw_t stage[DEPTH][CPT];
   u16x8 bcur[NB][3];
   load_tile(0, stage[0]);
   store_tile(0, stage[0]);
@@ -173,57 +185,88 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
 
   // epilogue: lane holds rows m = mwg + (rb0 + mb)*16 + 4g + t (t < 4), column a = (cb0 + nb)*16 + l16
   const long long r_lo = mwg / PQ;
-  [[maybe_unused]] NormAcc na;
+  // Divide: every eigenvalue load is issued before the first store.  The vector-memory
+  // counter also counts stores, so a load issued after a store would wait for the store.
+  // The parts of the denominator are summed in FP64 and rounded once to FP32, the precision
+  // of the data.  An exact FP64 cancellation lamz + shift = 0 stays exact after rounding
+  // (the two roundings are negatives of each other), so the FP32 zero test sees the null mode.
+  [[maybe_unused]] float shift[EPI == EPI_DIVIDE ? MB : 1][4];
+  [[maybe_unused]] float lamz_c[EPI == EPI_DIVIDE ? NB : 1];
+  if constexpr (EPI == EPI_DIVIDE) {
+    if (PQ >= MT) {
+      // a tile meets at most one RHS boundary: branch-free row split, so the 4 * MB loads issue
+      // back to back (rows past the end read the last row; their results are not stored)
+      const double sg0 = ep.sigma[r_lo];
+      const double sg1 = r_lo + 1 < R ? ep.sigma[r_lo + 1] : 0.0;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const long long o = min(mq + t, Mrows - 1) - r_lo * PQ;
+          const bool nxt = o >= PQ;
+          shift[mb][t] = static_cast<float>(ep.lamxy[nxt ? o - PQ : o] + (nxt ? sg1 : sg0));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const long long r = rhs_of_row(mq + t, r_lo, PQ);
+          shift[mb][t] = (mq + t < Mrows) ? static_cast<float>(ep.lamxy[mq + t - r * PQ] + ep.sigma[r]) : 1.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int a = (cb0 + nb) * 16 + l16;
+      lamz_c[nb] = a < K ? static_cast<float>(ep.lamz[a]) : 1.f;
+    }
+  }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;  // first of the lane's four rows
     long long rr[4], pq[4];
-    [[maybe_unused]] double shift[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       rr[t] = rhs_of_row(mq + t, r_lo, PQ);
       pq[t] = mq + t - rr[t] * PQ;
-      if constexpr (EPI == EPI_DIVIDE) {
-        const int pqi = static_cast<int>(pq[t]);
-        const int b = pqi / ep.nx;
-        shift[t] = (mq + t < Mrows) ? ep.lamx[pqi - b * ep.nx] + ep.lamy[b] + ep.sigma[rr[t]] : 1.0;
-      }
     }
     const bool full = VEC && (mq + 3 < Mrows);  // the four rows share one RHS and are aligned
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int a = (cb0 + nb) * 16 + l16;
       if (a >= K) continue;
-      if constexpr (EPI == EPI_ACCUM) {
+      if constexpr (EPI == EPI_STORE_F64) {
         double* Y = static_cast<double*>(Yv);
+        const f4 v = acc[mb][nb];
         if (full) {
-          d4v* p = reinterpret_cast<d4v*>(Y + (rr[0] * K + a) * PQ + pq[0]);
-          d4v un = ep.accum_zero ? d4v{0, 0, 0, 0} : *p;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const double du = static_cast<double>(acc[mb][nb][t]);
-            un[t] += du;
-            na.add(ep, r_lo, rr[0], du, un[t]);
-          }
-          *p = un;
+          *reinterpret_cast<d4v*>(Y + (rr[0] * K + a) * PQ + pq[0]) =
+              d4v{static_cast<double>(v[0]), static_cast<double>(v[1]), static_cast<double>(v[2]),
+                  static_cast<double>(v[3])};
         } else {
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (mq + t >= Mrows) continue;
-            const long long idx = (rr[t] * K + a) * PQ + pq[t];
-            const double du = static_cast<double>(acc[mb][nb][t]);
-            const double un = (ep.accum_zero ? 0.0 : Y[idx]) + du;
-            Y[idx] = un;
-            na.add(ep, r_lo, rr[t], du, un);
-          }
+          for (int t = 0; t < 4; ++t)
+            if (mq + t < Mrows) Y[(rr[t] * K + a) * PQ + pq[t]] = static_cast<double>(v[t]);
         }
       } else {
         float* Y = static_cast<float*>(Yv);
         f4 v = acc[mb][nb];
         if constexpr (EPI == EPI_DIVIDE) {
+          // FP32 divide: rcp estimate + one Newton step
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            v[t] = static_cast<float>(divide_by_eigs(static_cast<double>(v[t]), ep, a, shift[t]));
+          for (int t = 0; t < 4; ++t) {
+            const float d = lamz_c[nb] + shift[mb][t];
+            if (d == 0.f) {
+              v[t] = ep.eq28 ? v[t] : 0.f;
+            } else {
+              float r = __builtin_amdgcn_rcpf(d);
+              r = fmaf(r, fmaf(-d, r, 1.f), r);
+              v[t] *= r;
+            }
+          }
         }
         if (full) {
           *reinterpret_cast<f4*>(Y + (rr[0] * K + a) * PQ + pq[0]) = v;
@@ -235,7 +278,6 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
       }
     }
   }
-  if constexpr (EPI == EPI_ACCUM) na.flush(ep, r_lo, R, lane);
 }
 
 // Row blocks per wave for the rotating kernel with table entry c: 128-row workgroup tiles

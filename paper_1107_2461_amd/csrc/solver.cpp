@@ -187,10 +187,18 @@ struct helm_plan {
   bool all_neumann = false;
   int device = 0;
   unsigned long long* host_norms = nullptr;  // pinned, 2 * kMaxRhs * kNormStripes
+  double* lamxy = nullptr;                   // device, m[0] * m[1]: lamx[a] + lamy[b] (split-BF16)
   std::mutex mu;                             // guards host_norms
   mutable StageProfiler prof;
   ~helm_plan() {
     if (host_norms) (void)hipHostFree(host_norms);
+    if (lamxy) {
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      (void)hipSetDevice(device);
+      (void)hipFree(lamxy);
+      (void)hipSetDevice(cur);
+    }
   }
   long long npts() const { return static_cast<long long>(m[0]) * m[1] * m[2]; }
   bool refined() const {
@@ -309,6 +317,16 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
   if (hipHostMalloc(reinterpret_cast<void**>(&p->host_norms),
                     2 * kMaxRhs * kNormStripes * sizeof(unsigned long long)) != hipSuccess)
     return HELM_ENOMEM;
+  if (p->prec() == P_BF16X3) {
+    // per-(a, b) part of the eq. 26-27 denominator, summed in FP64 once per plan
+    const std::vector<double>& lx = p->ax[0]->host.lam;
+    const std::vector<double>& ly = p->ax[1]->host.lam;
+    std::vector<double> t(static_cast<size_t>(p->m[0]) * p->m[1]);
+    for (int b = 0; b < p->m[1]; ++b)
+      for (int a = 0; a < p->m[0]; ++a) t[static_cast<size_t>(b) * p->m[0] + a] = lx[a] + ly[b];
+    const hipError_t e = upload(&p->lamxy, t.data(), t.size());
+    if (e != hipSuccess) return from_hip(e);
+  }
   *out = p.release();
   return HELM_OK;
 }
@@ -400,7 +418,8 @@ hipError_t timed(const helm_plan* p, int stage, hipStream_t st, F&& launch) {
 // final x-inverse output.  bufs: two scratch buffers of type pr; the final product writes
 // `out` with epilogue epi_last (STORE in pr, or ACCUM into FP64 u).
 hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, void* b2, void* out, Epi epi_last,
-                        int nrhs, const double* sig, unsigned long long* norms, int accum_zero, hipStream_t st) {
+                        int nrhs, const double* sig, unsigned long long* norms, int accum_zero, hipStream_t st,
+                        bool in_f64 = false) {
   const DevAxis& X = *p->ax[0];
   const DevAxis& Y = *p->ax[1];
   const DevAxis& Z = *p->ax[2];
@@ -409,6 +428,7 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   ep.lamx = X.lam;
   ep.lamy = Y.lam;
   ep.lamz = Z.lam;
+  ep.lamxy = p->lamxy;
   ep.nx = static_cast<int>(nx);
   ep.eq28 = p->opts.null_mode == HELM_NULL_PAPER_EQ28;
   ep.norms = norms;
@@ -418,37 +438,43 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   hipError_t e;
   if (pr == P_BF16X3) {
     // rotating layout: [k][j][i] -> [a][k][j] -> [b][a][k] -> [c][b][a] -> [i][c][b] -> [j][i][c] -> [k][j][i]
-    const float* fin = static_cast<const float*>(in);
     float* f1 = static_cast<float*>(b1);
     float* f2 = static_cast<float*>(b2);
     if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
-           return mode_rot(X.sw3[0], nx, fin, f1, nrhs, ny * nz, EPI_STORE, ep, st);
+           return mode_rot(X.sw3[0], nx, in, in_f64, f1, nrhs, ny * nz, EPI_STORE, ep, st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
-           return mode_rot(Y.sw3[0], ny, f1, f2, nrhs, nz * nx, EPI_STORE, ep, st);
+           return mode_rot(Y.sw3[0], ny, f1, false, f2, nrhs, nz * nx, EPI_STORE, ep, st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_Z_FWD_DIV, st, [&] {
-           return mode_rot(Z.sw3[0], nz, f2, f1, nrhs, nx * ny, EPI_DIVIDE, ep, st);
+           return mode_rot(Z.sw3[0], nz, f2, false, f1, nrhs, nx * ny, EPI_DIVIDE, ep, st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_X_INV, st, [&] {
-           return mode_rot(X.sw3[1], nx, f1, f2, nrhs, nz * ny, EPI_STORE, ep, st);
+           return mode_rot(X.sw3[1], nx, f1, false, f2, nrhs, nz * ny, EPI_STORE, ep, st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_Y_INV, st, [&] {
-           return mode_rot(Y.sw3[1], ny, f2, f1, nrhs, nx * nz, EPI_STORE, ep, st);
-         })) != hipSuccess)
-      return e;
-    // the correction lands in FP32 (natural layout) and is added to u by a streaming kernel
-    if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
-           return mode_rot(Z.sw3[1], nz, f1, f2, nrhs, ny * nx, EPI_STORE, ep, st);
+           return mode_rot(Y.sw3[1], ny, f2, false, f1, nrhs, nx * nz, EPI_STORE, ep, st);
          })) != hipSuccess)
       return e;
     if (epi_last != EPI_ACCUM) return hipErrorInvalidValue;
+    if (accum_zero) {
+      // first solve (u = 0): the product writes u in FP64 directly; its norms are not used
+      return timed(p, HELM_STAGE_Z_INV, st, [&] {
+        return mode_rot(Z.sw3[1], nz, f1, false, out, nrhs, ny * nx, EPI_STORE_F64, ep, st);
+      });
+    }
+    // a correction lands in FP32 (natural layout) and is added to u by a streaming kernel
+    // that also takes the norms the refinement loop stops on
+    if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
+           return mode_rot(Z.sw3[1], nz, f1, false, f2, nrhs, ny * nx, EPI_STORE, ep, st);
+         })) != hipSuccess)
+      return e;
     return timed(p, HELM_STAGE_UPDATE, st, [&] {
-      return update_u(static_cast<double*>(out), f2, nx * ny * nz, nrhs, accum_zero, norms, st);
+      return update_u(static_cast<double*>(out), f2, nx * ny * nz, nrhs, 0, norms, st);
     });
   }
   const int ip = static_cast<int>(pr);
@@ -622,8 +648,13 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   const Prec store = pr == P_BF16X3 ? P_F32 : pr;  // storage type of the low-precision fields
   // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.
   if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
-  if (e == hipSuccess) e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, store, sa, st); });
-  if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st);
+  if (pr == P_BF16X3) {  // the first product reads f in FP64 directly
+    if (e == hipSuccess) e = tpf_products(p, pr, f, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st, true);
+  } else {
+    if (e == hipSuccess)
+      e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, store, sa, st); });
+    if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st);
+  }
   if (e != hipSuccess) return from_hip(e);
   if (!p->refined()) return from_hip(project_null());
   std::lock_guard<std::mutex> lk(p->mu);
