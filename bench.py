@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 6}
 ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}
 RIDGE = {k: v * 1e12 / (HBM_PEAK_GBS * 1e9) for k, v in MFMA_PEAK_TFLOPS.items()}
-MODE_STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv")
+MODE_STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv", "x_fwd_rhs", "z_inv_u")
 
 
 def log(*a):
@@ -57,11 +57,12 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
     if stage in MODE_STAGES:
         flops = 2.0 * N[stage] * npts
         es = ELEM_BYTES[prec]
-        # the last product writes the FP64 solution (the split-BF16 path writes an FP32
-        # correction instead, added by the separate update stage)
+        # FP64 solve: reads f, writes u.  Low-precision refinement: the last product adds its
+        # correction into u.  Split-BF16: the first solve reads f (x_fwd_rhs) and writes u
+        # (z_inv_u) in FP64; later corrections are FP32, added by the separate update stage.
         last = "none" if prec == "bf16x3" else "x_inv"
-        s_in = 8 if (stage == "x_fwd" and prec == "fp64") else es
-        s_out = 8 if stage == last else es
+        s_in = 8 if ((stage == "x_fwd" and prec == "fp64") or stage == "x_fwd_rhs") else es
+        s_out = 8 if (stage == last or stage == "z_inv_u") else es
         byts = (s_in + s_out) * npts
         if stage == last and prec != "fp64":
             byts = (es + 16) * npts          # read du (low), read + write u (FP64)
@@ -95,7 +96,31 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     for _ in range(warmup):
         plan.solve(f_dev, out=u, workspace=ws)
     torch.cuda.synchronize()
+    N = dict(x_fwd=prob.shape_xyz[0], x_inv=prob.shape_xyz[0], y_fwd=prob.shape_xyz[1], y_inv=prob.shape_xyz[1],
+             z_fwd_div=prob.shape_xyz[2], z_inv=prob.shape_xyz[2], x_fwd_rhs=prob.shape_xyz[0],
+             z_inv_u=prob.shape_xyz[2])
+    lowp = {"fp64": "fp64", "tpt": "fp64", "fp32_ir": "fp32", "bf16_ir": "bf16", "bf16x3_ir": "bf16x3"}[path]
+    npts = prob.npts * nrhs
+    # 1) per-stage table from a short run with every launch bracketed by events
+    prof_steps = max(1, min(steps, 5))
     plan.profile(True)
+    plan.profile_read()
+    for _ in range(prof_steps):
+        plan.solve(f_dev, out=u, workspace=ws)
+    torch.cuda.synchronize()
+    stages = plan.profile_read()
+    st = {}
+    for name, (ms, n) in stages.items():
+        rl = stage_roofline(name, ms, n, N, npts, lowp)
+        entry = dict(total_ms_per_step=ms / prof_steps, launches_per_step=n / prof_steps)
+        if rl:
+            entry.update(rl)
+            entry["frac"] = rl["achieved"] / rl["peak"]
+        st[name] = entry
+    # dominant kernel: the stage with the largest time per solve
+    dom = max((k for k in st if "bound" in st[k]), key=lambda k: st[k]["total_ms_per_step"])
+    # 2) the timed run: only the dominant stage's launches are bracketed (on the solve's stream)
+    plan.profile(True, stages=[dom])
     plan.profile_read()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     sweeps = []
@@ -108,11 +133,13 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
         sweeps.append(plan.last_info["sweeps"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stages = plan.profile_read()
+    timed = plan.profile_read()
     plan.profile(False)
+    dms, dn = timed[dom]
+    dom_rl = stage_roofline(dom, dms, dn, N, npts, lowp)
+    dom_rl["frac"] = dom_rl["achieved"] / dom_rl["peak"]
     lat_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     total_ms = ev[0].elapsed_time(ev[steps])
-    npts = prob.npts * nrhs
     res = dict(ms_per_step=total_ms / steps, wall_ms_per_step=wall * 1e3 / steps,
                pts_per_s=npts / (total_ms / steps / 1e3), p50_ms=float(np.percentile(lat_ms, 50)),
                p99_ms=float(np.percentile(lat_ms, 99)), sweeps=int(np.median(sweeps)))
@@ -129,18 +156,8 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     fr = f_dev.reshape(nrhs, -1)
     rr = (fr - hu.reshape(nrhs, -1)).norm(dim=1) / fr.norm(dim=1)
     res["rel_residual"] = float(rr.max())
-    N = dict(x_fwd=prob.shape_xyz[0], x_inv=prob.shape_xyz[0], y_fwd=prob.shape_xyz[1], y_inv=prob.shape_xyz[1],
-             z_fwd_div=prob.shape_xyz[2], z_inv=prob.shape_xyz[2])
-    lowp = {"fp64": "fp64", "tpt": "fp64", "fp32_ir": "fp32", "bf16_ir": "bf16", "bf16x3_ir": "bf16x3"}[path]
-    st = {}
-    for name, (ms, n) in stages.items():
-        rl = stage_roofline(name, ms, n, N, npts, lowp)
-        entry = dict(total_ms_per_step=ms / steps, launches_per_step=n / steps)
-        if rl:
-            entry.update(rl)
-            entry["frac"] = rl["achieved"] / rl["peak"]
-        st[name] = entry
     res["stages"] = st
+    res["dominant"] = dict(kernel=dom, launches_per_step=dn / steps, **dom_rl)
     res["precision"] = lowp
     del plan
     return res
@@ -203,7 +220,10 @@ def committed_traffic(prec, stage):
     except (OSError, ValueError):
         return None
     ent = data.get(prec, {}).get(stage)
-    if not ent or ent.get("source_hash") != source_hash(prec):
+    if not ent:
+        return None
+    srcs = TRAFFIC_SOURCES.get(stage)
+    if ent.get("source_hash") != (source_hash(prec) if srcs is None else _hash_files(srcs)):
         return None
     return ent.get("bytes_per_launch")
 
@@ -277,6 +297,115 @@ def run_serving(torch, args):
     print(json.dumps(line))
 
 
+# ---------------------------------------------------------------------------------------
+# Profile summaries (profiles/*.md, profiles/traffic.json) from rocprofv3 CSV output.
+# Usage, after the three rocprofv3 runs listed in PROFILE_COMMANDS (run from the repo root):
+#   python bench.py --summarize-profiles gpurun_out/prof
+PROFILE_COMMANDS = (
+    "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/kt -o kt -- "
+    "python -u bench.py --steps 5 --warmup 1 --no-cpu-baseline",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fetch -o f -- "
+    "python -u bench.py --steps 2 --warmup 0 --no-cpu-baseline --paths bf16x3_ir,fp64 --copy-ref-mb 1024",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o w -- "
+    "python -u bench.py --steps 2 --warmup 0 --no-cpu-baseline --paths bf16x3_ir,fp64 --copy-ref-mb 1024",
+)
+# (path family, stage) -> (kernel name prefix in the trace, algorithmic bytes per point)
+TRAFFIC_STAGES = {
+    ("bf16x3", "z_fwd_div"): ("void helm::k_rot_bf16x3<4, 4, 8, 1, true, float>", 8),
+    ("bf16x3", "x_fwd"): ("void helm::k_rot_bf16x3<4, 4, 8, 0, true, float>", 8),
+    ("bf16x3", "x_fwd_rhs"): ("void helm::k_rot_bf16x3<4, 4, 8, 0, true, double>", 12),
+    ("bf16x3", "z_inv_u"): ("void helm::k_rot_bf16x3<4, 4, 8, 3, true, float>", 12),
+    ("bf16x3", "residual"): ("void helm::k_stencil<float, 1>", 20),
+    ("bf16x3", "update"): ("helm::k_update", 20),
+    ("fp64", "z_fwd_div"): ("void helm::k_left<double, 4, 4, 4, 1, 2, false>", 16),
+    ("fp64", "y_fwd"): ("void helm::k_left<double, 4, 4, 4, 0, 2, false>", 16),
+}
+TRAFFIC_SOURCES = {"residual": ["paper_1107_2461_amd/csrc/kernels.hip"], "update": ["paper_1107_2461_amd/csrc/kernels.hip"]}
+
+
+def _read_csv(pattern):
+    import csv
+    import glob
+    rows = []
+    for fn in sorted(glob.glob(pattern, recursive=True)):
+        with open(fn) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_profiles(d, copy_mb=1024, npts=256 ** 3, workload="256^3 Helmholtz (tau = 10)"):
+    import collections
+    prof_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(prof_dir, exist_ok=True)
+    cmds = [c.format(d=d) for c in PROFILE_COMMANDS]
+    # kernel durations
+    stats = _read_csv(os.path.join(d, "kt", "**", "*kernel_stats.csv"))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# Kernel durations, {workload}, all arithmetic paths", "", "Command (repo root, one MI355X):", "",
+             "```", cmds[0], "```", "", "Top 24 kernels by total time (`*_kernel_stats.csv`).", "",
+             "| calls | avg (us) | total (ms) | kernel |", "|---:|---:|---:|---|"]
+    for r in stats[:24]:
+        name = r["Name"] if len(r["Name"]) < 150 else r["Name"][:147] + "..."
+        lines.append(f"| {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | `{name}` |")
+    with open(os.path.join(prof_dir, "kernel_stats_helmholtz_256cube.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    # HBM traffic: per-dispatch counters, calibrated on the copy of copy_mb MiB
+    per = {}
+    scale = {}
+    for tag, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        rows = [r for r in _read_csv(os.path.join(d, tag, "**", "*counter_collection.csv"))
+                if r["Counter_Name"] == counter]
+        vals = collections.defaultdict(list)
+        for r in rows:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        copies = [v for k, vs in vals.items() if "copyBuffer" in k for v in vs]
+        scale[tag] = copy_mb * 1024.0 / max(copies)
+        per[tag] = {k: sum(v) / len(v) * 1024.0 * scale[tag] for k, v in vals.items()}
+
+    def lookup(tag, prefix):
+        hits = [v for k, v in per[tag].items() if k.startswith(prefix)]
+        return hits[0] if hits else None
+
+    traffic = {}
+    rows_md = []
+    for (fam, stage), (prefix, bpp) in TRAFFIC_STAGES.items():
+        rd, wr = lookup("fetch", prefix), lookup("write", prefix)
+        if rd is None or wr is None:
+            continue
+        srcs = TRAFFIC_SOURCES.get(stage)
+        h = source_hash(fam) if srcs is None else _hash_files(srcs)
+        traffic.setdefault(fam, {})[stage] = dict(bytes_per_launch=rd + wr, read_bytes=rd, write_bytes=wr,
+                                                  kernel=prefix, source_hash=h)
+        alg = bpp * npts
+        rows_md.append(f"| {fam} | {stage} | `{prefix}` | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {(rd + wr) / 1e6:.1f} | "
+                       f"{alg / 1e6:.1f} | {(rd + wr) / alg:.2f} |")
+    with open(os.path.join(prof_dir, "traffic.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    lines = [f"# HBM traffic per launch, {workload}", "", "Two counter runs (one counter each, repo root, one MI355X):",
+             "", "```", cmds[1], cmds[2], "```", "",
+             f"Calibration: the {copy_mb} MiB device copy (`__amd_rocclr_copyBuffer`) gives FETCH_SIZE x "
+             f"{scale['fetch']:.4f} and WRITE_SIZE x {scale['write']:.4f} (bytes = counter KiB x 1024 x scale).",
+             "These are L2-miss bytes, an upper bound on HBM bytes.  Summary written by "
+             "`python bench.py --summarize-profiles <dir>`.", "",
+             "| path | stage | kernel | read MB | write MB | total MB | algorithmic MB | ratio |",
+             "|---|---|---|---:|---:|---:|---:|---:|"] + rows_md + [
+             "", "`traffic.json` holds these per-launch totals for bench.py's `roofline.traffic`, with a hash of the",
+             "kernel sources they were measured on (bench.py reports null once those sources change)."]
+    with open(os.path.join(prof_dir, "hbm_traffic_helmholtz_256cube.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    log(f"[bench] profiles written from {d}")
+
+
+def _hash_files(rels):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in rels:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +423,12 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-paths", default="bf16x3_ir,fp64")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write profiles/*.md and profiles/traffic.json from rocprofv3 output under DIR")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps(dict(error="this solver benchmark runs on exactly one GPU; the multi-GPU (z-slab + "
                                     "all-to-all) decomposition is not built", n_gpus=args.gpus)))
@@ -333,10 +467,9 @@ def main():
     ok = {k: v for k, v in results.items() if v.get("err_vs_oracle_samples", v["rel_residual"]) <= 1e-10}
     best = max(ok, key=lambda k: ok[k]["pts_per_s"]) if ok else max(results, key=lambda k: results[k]["pts_per_s"])
     b = results[best]
-    # dominant kernel of the headline path: the stage with the largest time per step
-    dom = max((s for s in b["stages"] if "bound" in b["stages"][s]),
-              key=lambda s: b["stages"][s]["total_ms_per_step"])
-    d = b["stages"][dom]
+    # dominant kernel of the headline path, timed inside the timed region
+    d = b["dominant"]
+    dom = d["kernel"]
     roofline = dict(kernel=dom, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
                     frac=d["frac"], traffic=committed_traffic(b["precision"], dom), avg_us=d["avg_us"],
                     algorithmic_bytes=d.get("algorithmic_bytes"), algorithmic_flops=d.get("algorithmic_flops"))

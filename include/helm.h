@@ -188,10 +188,17 @@ void helm_pmatrix_destroy(helm_pmat* pm);
 enum {
   HELM_STAGE_X_FWD = 0, HELM_STAGE_Y_FWD, HELM_STAGE_Z_FWD_DIV, HELM_STAGE_Z_INV, HELM_STAGE_Y_INV,
   HELM_STAGE_X_INV, HELM_STAGE_THOMAS, HELM_STAGE_NULL_LINE, HELM_STAGE_RESIDUAL, HELM_STAGE_CONVERT,
-  HELM_STAGE_APPLY, HELM_STAGE_OTHER, HELM_STAGE_UPDATE, HELM_NSTAGES
+  HELM_STAGE_APPLY, HELM_STAGE_OTHER, HELM_STAGE_UPDATE,
+  /* split-BF16 first solve: the x-forward product reading the FP64 right-hand side, and the
+   * z-inverse product writing the FP64 solution */
+  HELM_STAGE_X_FWD_RHS, HELM_STAGE_Z_INV_U, HELM_NSTAGES
 };
 helm_status helm_profile_enable(helm_plan* plan, int enable);
 helm_status helm_profile_read(helm_plan* plan, double* ms, int* launches);
+/* Restricts timing to the stages whose bit (1u << stage) is set in stage_mask (default: all),
+ * so that a timed run can bracket only the kernel it measures; clears the records.
+ * Returns EINVAL for a null plan or a mask with no valid stage bit. */
+helm_status helm_profile_stages(helm_plan* plan, unsigned stage_mask);
 
 /* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of solve requests on one GPU.

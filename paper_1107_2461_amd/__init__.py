@@ -161,9 +161,17 @@ class Plan:
                                 _stream_ptr(stream)), "helm_apply")
         return out[0] if u.dim() == 3 else out
 
-    def profile(self, enable=True):
-        """Enable/disable per-launch stage timing (helm_profile_enable)."""
-        check(load().helm_profile_enable(self._h, int(bool(enable))), "helm_profile_enable")
+    def profile(self, enable=True, stages=None):
+        """Enable/disable per-launch stage timing (helm_profile_enable); `stages` (names from
+        STAGES) restricts it to those stages (helm_profile_stages), None times all of them."""
+        lib = load()
+        mask = ~0 & 0xFFFFFFFF
+        if stages is not None:
+            mask = 0
+            for name in stages:
+                mask |= 1 << _lib.STAGES.index(name)
+        check(lib.helm_profile_stages(self._h, C.c_uint(mask)), "helm_profile_stages")
+        check(lib.helm_profile_enable(self._h, int(bool(enable))), "helm_profile_enable")
 
     def profile_read(self):
         """{stage: (milliseconds, launches)} accumulated since the last read (helm_profile_read)."""

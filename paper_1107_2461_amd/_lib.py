@@ -14,7 +14,7 @@ FP64, FP32, BF16, FP32_IR, BF16_IR, BF16X3, BF16X3_IR = range(7)
 TPF, TPT_Z = 0, 1
 NULL_PROJECT, NULL_PAPER_EQ28 = 0, 1
 STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv", "thomas", "null_line", "residual", "convert",
-          "apply", "other", "update")
+          "apply", "other", "update", "x_fwd_rhs", "z_inv_u")
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp32_ir": FP32_IR, "bf16_ir": BF16_IR, "bf16x3": BF16X3,
               "bf16x3_ir": BF16X3_IR}
@@ -70,6 +70,7 @@ SIGNATURES = {
     "helm_pmatrix_destroy": (None, [P]),
     "helm_profile_enable": (C.c_int, [P, C.c_int]),
     "helm_profile_read": (C.c_int, [P, DP, IP]),
+    "helm_profile_stages": (C.c_int, [P, C.c_uint]),
     "helm_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_double, C.POINTER(HelmOpts), C.POINTER(P)]),
     "helm_server_submit": (C.c_int, [P, C.POINTER(HelmGrid), C.POINTER(HelmBC), DP, C.c_int, P, P, C.c_longlong]),
     "helm_server_poll": (C.c_int, [P, C.POINTER(HelmRequestRecord), C.c_int, IP, C.c_int]),

@@ -155,6 +155,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Optional per-launch event timing (helm_profile_enable / helm_profile_read).
 struct StageProfiler {
   bool on = false;
+  unsigned mask = ~0u;  // stages timed when on
   struct Rec {
     int stage;
     hipEvent_t a, b;
@@ -402,7 +403,7 @@ struct DeviceGuard {
 
 template <typename F>
 hipError_t timed(const helm_plan* p, int stage, hipStream_t st, F&& launch) {
-  if (!p->prof.on) return launch();
+  if (!p->prof.on || !((p->prof.mask >> stage) & 1u)) return launch();
   hipEvent_t a = p->prof.take(), b = p->prof.take();
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, st);
@@ -440,7 +441,7 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
     // rotating layout: [k][j][i] -> [a][k][j] -> [b][a][k] -> [c][b][a] -> [i][c][b] -> [j][i][c] -> [k][j][i]
     float* f1 = static_cast<float*>(b1);
     float* f2 = static_cast<float*>(b2);
-    if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
+    if ((e = timed(p, in_f64 ? HELM_STAGE_X_FWD_RHS : HELM_STAGE_X_FWD, st, [&] {
            return mode_rot(X.sw3[0], nx, in, in_f64, f1, nrhs, ny * nz, EPI_STORE, ep, st);
          })) != hipSuccess)
       return e;
@@ -463,7 +464,7 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
     if (epi_last != EPI_ACCUM) return hipErrorInvalidValue;
     if (accum_zero) {
       // first solve (u = 0): the product writes u in FP64 directly; its norms are not used
-      return timed(p, HELM_STAGE_Z_INV, st, [&] {
+      return timed(p, HELM_STAGE_Z_INV_U, st, [&] {
         return mode_rot(Z.sw3[1], nz, f1, false, out, nrhs, ny * nx, EPI_STORE_F64, ep, st);
       });
     }
@@ -731,6 +732,13 @@ extern "C" helm_status helm_pressure_solve(helm_plan* p, const double* f, double
 extern "C" helm_status helm_profile_enable(helm_plan* p, int enable) {
   if (!p) return HELM_EINVAL;
   p->prof.on = enable != 0;
+  p->prof.clear();
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_profile_stages(helm_plan* p, unsigned stage_mask) {
+  if (!p || (stage_mask & ((1u << HELM_NSTAGES) - 1u)) == 0) return HELM_EINVAL;
+  p->prof.mask = stage_mask;
   p->prof.clear();
   return HELM_OK;
 }
