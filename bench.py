@@ -228,6 +228,63 @@ def committed_traffic(prec, stage):
     return ent.get("bytes_per_launch")
 
 
+def run_pressure_matrix(torch, prob, f, tau, precision, steps):
+    """FGMRES(30) on the pressure matrix C of eq. 9 (velocity Helmholtz plans with sigma = 1/tau),
+    to a 1e-10 relative residual, without and with the two preconditioners."""
+    from paper_1107_2461_amd import PressureMatrix
+    pm = PressureMatrix(prob.faces, tau, precision=precision)
+    b = torch.from_numpy(f[0]).cuda()
+    out = {}
+    for pc, name in ((0, "none"), (1, "pressure_laplacian"), (2, "cahouet_chabard")):
+        pm.solve(b, tol=1e-10, max_it=500, restart=30, precondition=pc)   # warm-up (plans, workspace)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            p = pm.solve(b, tol=1e-10, max_it=500, restart=30, precondition=pc)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        info = pm.last_info
+        r = float((b - pm.apply(p)).norm() / b.norm())
+        out[name] = dict(iterations=info["iterations"], converged=bool(info["converged"]), rel_residual=r,
+                         ms_per_solve=1e3 * float(np.median(ts)))
+        log(f"[bench] FGMRES precond={name}: {info['iterations']} it, res {r:.2e}, "
+            f"{out[name]['ms_per_solve']:.1f} ms")
+    del pm
+    return out
+
+
+def run_pressure(torch, args):
+    """The pressure workload: all-Neumann pressure Laplacian solves (eq. 28) and FGMRES on the
+    pressure matrix C (eq. 9) with tau = 100."""
+    prob, f = workloads.workload_pressure()
+    gp = os.path.join(ROOT, "tests", "golden", "oracle_samples_c4_pressure.json")
+    golden = json.load(open(gp)) if os.path.exists(gp) else None
+    f_dev = torch.from_numpy(f).to("cuda")
+    results = {}
+    for path in ("fp64", "bf16x3_ir"):
+        log(f"[bench] pressure path {path} ...")
+        results[path] = run_path(torch, prob, f_dev, path, args.steps, args.warmup, golden, 1)
+        log(f"[bench] {path}: {results[path]['ms_per_step']:.3f} ms/solve, err "
+            f"{results[path].get('err_vs_oracle_samples')}")
+    ok = {k: v for k, v in results.items() if v.get("err_vs_oracle_samples", v["rel_residual"]) <= 1e-10}
+    best = max(ok or results, key=lambda k: results[k]["pts_per_s"])
+    b = results[best]
+    d = b["dominant"]
+    fg = run_pressure_matrix(torch, prob, f, 1e2, "fp64", max(1, min(args.steps, 3)))
+    line = dict(metric="grid-pts/s per pressure (all-Neumann) solve @1e-10 rel err", value=b["pts_per_s"],
+                unit="grid-pts/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=b["ms_per_step"],
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype=b["precision"], data="synthetic",
+                config=dict(workload=prob.name, grid=list(prob.shape_xyz), stretch=1.5, nrhs=1, sigma=0.0,
+                            path=best),
+                p50_ms=b["p50_ms"], p99_ms=b["p99_ms"],
+                roofline=dict(kernel=d["kernel"], bound=d["bound"], achieved=d["achieved"], peak=d["peak"],
+                              unit=d["unit"], frac=d["frac"], traffic=None, avg_us=d["avg_us"]),
+                cpu_baseline=None, fgmres_tau100=fg,
+                paths={k: {kk: vv for kk, vv in v.items()} for k, v in results.items()})
+    print(json.dumps(line))
+
+
 def run_serving(torch, args):
     """Serving stream: Poisson arrivals of mixed solve requests through the continuous-batching server."""
     from paper_1107_2461_amd import Server
@@ -411,7 +468,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mixed_256")
+    ap.add_argument("--workload", default="mixed_256",
+                    help="mixed_256 (default), multirhs_128, small_32, pressure, serving")
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -441,6 +499,9 @@ def main():
     load()
     if args.workload == "serving":
         run_serving(torch, args)
+        return
+    if args.workload == "pressure":
+        run_pressure(torch, args)
         return
     prob, f, gname, extra = build_workload(args.workload)
     golden = None

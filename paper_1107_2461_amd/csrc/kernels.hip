@@ -476,6 +476,9 @@ hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st) {
 
 // Deterministic volume-weighted sums: stage 1 writes one partial per block, stage 2 sums
 // them in a fixed order, stage 3 subtracts the mean.
+// Volume-weighted sum, deterministic: workgroup g of a RHS takes the x-rows q = g, g + G, ...
+// (q = k * ny + j, weight vz[k] vy[j] per row) with its lanes striding the row, then a fixed
+// tree in LDS; the G partials are summed by one workgroup in a fixed tree as well.
 __global__ __launch_bounds__(256) void k_wsum_partial(const double* __restrict__ x, const double* __restrict__ vx,
                                                       const double* __restrict__ vy, const double* __restrict__ vz,
                                                       int nx, int ny, int nz, int blocks_per_rhs,
@@ -484,14 +487,15 @@ __global__ __launch_bounds__(256) void k_wsum_partial(const double* __restrict__
   const int r = blockIdx.y;
   const long long P = static_cast<long long>(nx) * ny * nz;
   const double* xr = x + r * P;
+  const int rows = ny * nz;
   double s = 0.0;
-  for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < P;
-       i += static_cast<long long>(blocks_per_rhs) * 256) {
-    const int a = static_cast<int>(i % nx);
-    const long long t = i / nx;
-    const int b = static_cast<int>(t % ny);
-    const int c = static_cast<int>(t / ny);
-    s += vz[c] * vy[b] * vx[a] * xr[i];
+#pragma unroll 4
+  for (int q = blockIdx.x; q < rows; q += blocks_per_rhs) {
+    const int c = q / ny, b = q - c * ny;
+    const double* row = xr + static_cast<long long>(q) * nx;
+    double t = 0.0;
+    for (int a = threadIdx.x; a < nx; a += 256) t += vx[a] * row[a];
+    s += vz[c] * vy[b] * t;
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -501,13 +505,19 @@ __global__ __launch_bounds__(256) void k_wsum_partial(const double* __restrict__
   }
   if (threadIdx.x == 0) part[static_cast<long long>(r) * blocks_per_rhs + blockIdx.x] = sh[0];
 }
-__global__ void k_wsum_final(double* part, int blocks_per_rhs, double inv_volsum, double* mean) {
+__global__ __launch_bounds__(256) void k_wsum_final(const double* __restrict__ part, int blocks_per_rhs,
+                                                    double inv_volsum, double* __restrict__ mean) {
+  __shared__ double sh[256];
   const int r = blockIdx.x;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < blocks_per_rhs; ++i) s += part[static_cast<long long>(r) * blocks_per_rhs + i];
-    mean[r] = s * inv_volsum;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < blocks_per_rhs; i += 256) s += part[static_cast<long long>(r) * blocks_per_rhs + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) mean[r] = sh[0] * inv_volsum;
 }
 __global__ __launch_bounds__(256) void k_sub_mean(double* x, const double* mean, long long P,
                                                   unsigned long long mask) {
@@ -524,7 +534,7 @@ hipError_t remove_mean(double* x, const double* volx, const double* voly, const 
   double* mean = scratch + static_cast<long long>(nrhs) * kMeanBlocks;
   hipLaunchKernelGGL(k_wsum_partial, dim3(kMeanBlocks, nrhs), dim3(256), 0, st, x, volx, voly, volz, nx, ny, nz,
                      kMeanBlocks, part);
-  hipLaunchKernelGGL(k_wsum_final, dim3(nrhs), dim3(64), 0, st, part, kMeanBlocks, inv_volsum, mean);
+  hipLaunchKernelGGL(k_wsum_final, dim3(nrhs), dim3(256), 0, st, part, kMeanBlocks, inv_volsum, mean);
   const long long P = static_cast<long long>(nx) * ny * nz;
   hipLaunchKernelGGL(k_sub_mean, dim3(static_cast<unsigned>((P + 255) / 256), nrhs), dim3(256), 0, st, x, mean, P,
                      mask);

@@ -107,7 +107,7 @@ hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign
 hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st);
 // Volume-weighted mean removal per RHS: x -= sum(vol * x) * inv_volsum   (FP64, in place,
 // deterministic order).  scratch: nrhs * (kMeanBlocks + 1) doubles of device memory.
-constexpr int kMeanBlocks = 512;
+constexpr int kMeanBlocks = 1024;
 // Only the RHS r with bit r of `mask` set are changed.
 hipError_t remove_mean(double* x, const double* volx, const double* voly, const double* volz,
                        int nx, int ny, int nz, int nrhs, double inv_volsum, unsigned long long mask,

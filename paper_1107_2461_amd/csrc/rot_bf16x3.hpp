@@ -229,10 +229,20 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   for (int mb = 0; mb < MB; ++mb) {
     const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;  // first of the lane's four rows
     long long rr[4], pq[4];
+    if (PQ >= MT) {  // at most one RHS boundary inside the tile: branch-free split
+      const long long o = mq - r_lo * PQ;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      rr[t] = rhs_of_row(mq + t, r_lo, PQ);
-      pq[t] = mq + t - rr[t] * PQ;
+      for (int t = 0; t < 4; ++t) {
+        const bool nxt = o + t >= PQ;
+        rr[t] = r_lo + nxt;
+        pq[t] = nxt ? o + t - PQ : o + t;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        rr[t] = rhs_of_row(mq + t, r_lo, PQ);
+        pq[t] = mq + t - rr[t] * PQ;
+      }
     }
     const bool full = VEC && (mq + 3 < Mrows);  // the four rows share one RHS and are aligned
 #pragma unroll

@@ -553,9 +553,12 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* w = static_cast<unsigned char*>(ws);
   const Prec pr = p->prec();
-  // All-Neumann Laplace RHS (sigma = 0, projection mode): the constant is invisible to the
-  // operator, so rounding in the transforms (and every refinement sweep) can leave a small
-  // constant in u; it is removed at the end with an FP64 volume-weighted mean.
+  // All-Neumann Laplace RHS (sigma = 0, projection mode): the divide sets the null-mode
+  // coefficient to exactly zero, and the volume-weighted mean of u is that coefficient times a
+  // constant, so an FP64 solve leaves a mean at the rounding level (~1e-16 |u|) and needs no
+  // pass of its own.  A low-precision first solve leaks a constant at its own precision that
+  // no refinement sweep can see (H 1 = 0); it is removed at the end with an FP64
+  // volume-weighted mean.
   unsigned long long null_mask = 0;
   if (p->all_neumann && p->opts.null_mode == HELM_NULL_PROJECT)
     for (int r = 0; r < nrhs; ++r)
@@ -637,7 +640,6 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
           return mode_right(P_F64, X.sw[0][1], nx, W, P_F64, u, P_F64, nrhs * ny * nz, EPI_STORE, ep, st);
         });
     }
-    if (e == hipSuccess) e = project_null();
     return from_hip(e);
   }
 

@@ -105,6 +105,10 @@ def test_all_neumann_laplace_projection(torch, method):
     ref = _oracle(prob, f, method="splu")
     assert _per_rhs_err(u, ref) <= 1e-12                      # u has zero weighted mean already
     assert _per_rhs_err(_gauge(u, faces), ref) <= 1e-12
+    # the FP64 path has no projection pass: the zeroed null coefficient alone leaves the
+    # weighted mean at the rounding level
+    for r in range(2):
+        assert np.abs(u[r] - _gauge(u, faces)[r]).max() <= 1e-14 * np.abs(u[r]).max()
     # eq. 28 option: zero denominator replaced by 1 -> differs from the projection by a constant
     u28, _ = _solve(torch, prob, f, method=method, null_mode=1)
     d = u28 - u
