@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 
 namespace helm {
@@ -61,51 +62,57 @@ std::string build_operator_1d(int n, const double* faces, int loc, int bc_lo, in
   return "";
 }
 
-bool tridiag_eigen(int m, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Z) {
-  Z.assign(static_cast<size_t>(m) * m, 0.0);
-  for (int i = 0; i < m; ++i) Z[static_cast<size_t>(i) * m + i] = 1.0;
+namespace {
+
+// Implicit QL with shifts on a symmetric tridiagonal matrix (d: diagonal, e: off-diagonal,
+// e[i] couples i and i + 1), accumulating the rotations into Z (row-major, Z[k][a] =
+// component k of vector a).  On return d holds the eigenvalues in ascending order.
+template <typename R>
+bool tridiag_ql(int m, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Z) {
+  Z.assign(static_cast<size_t>(m) * m, R(0));
+  for (int i = 0; i < m; ++i) Z[static_cast<size_t>(i) * m + i] = R(1);
   e.resize(m);
-  e[m - 1] = 0.0;
-  const double eps = std::numeric_limits<double>::epsilon();
+  e[m - 1] = R(0);
+  const R eps = std::numeric_limits<R>::epsilon();
   for (int l = 0; l < m; ++l) {
     int iter = 0;
     for (;;) {
       // Look for a negligible off-diagonal element splitting the matrix at or below l.
       int s = l;
       for (; s < m - 1; ++s) {
-        const double dd = std::fabs(d[s]) + std::fabs(d[s + 1]);
+        const R dd = std::fabs(d[s]) + std::fabs(d[s + 1]);
         if (std::fabs(e[s]) <= eps * dd) break;
       }
       if (s == l) break;
       if (++iter > 60) return false;
       // Shift from the leading 2x2 block (Wilkinson-type), then chase the bulge upward
       // from s to l with plane rotations, accumulating them into Z.
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
-      g = d[s] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-      double sn = 1.0, cs = 1.0, p = 0.0;
+      R g = (d[l + 1] - d[l]) / (R(2) * e[l]);
+      R r = std::hypot(g, R(1));
+      g = d[s] - d[l] + e[l] / (g + (g >= R(0) ? r : -r));
+      R sn = R(1), cs = R(1), p = R(0);
       int i = s - 1;
       bool underflow = false;
       for (; i >= l; --i) {
-        double f = sn * e[i];
-        const double b = cs * e[i];
+        R f = sn * e[i];
+        const R b = cs * e[i];
         r = std::hypot(f, g);
         e[i + 1] = r;
-        if (r == 0.0) {
+        if (r == R(0)) {
           d[i + 1] -= p;
-          e[s] = 0.0;
+          e[s] = R(0);
           underflow = true;
           break;
         }
         sn = f / r;
         cs = g / r;
         g = d[i + 1] - p;
-        r = (d[i] - g) * sn + 2.0 * cs * b;
+        r = (d[i] - g) * sn + R(2) * cs * b;
         p = sn * r;
         d[i + 1] = g + p;
         g = cs * r - b;
         for (int k = 0; k < m; ++k) {
-          double* zk = &Z[static_cast<size_t>(k) * m];
+          R* zk = &Z[static_cast<size_t>(k) * m];
           f = zk[i + 1];
           zk[i + 1] = sn * zk[i] + cs * f;
           zk[i] = cs * zk[i] - sn * f;
@@ -114,14 +121,14 @@ bool tridiag_eigen(int m, std::vector<double>& d, std::vector<double>& e, std::v
       if (underflow) continue;
       d[l] -= p;
       e[l] = g;
-      e[s] = 0.0;
+      e[s] = R(0);
     }
   }
   // Sort ascending, permuting the eigenvector columns alongside.
   std::vector<int> order(m);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
-  std::vector<double> d2(m), Z2(static_cast<size_t>(m) * m);
+  std::vector<R> d2(m), Z2(static_cast<size_t>(m) * m);
   for (int a = 0; a < m; ++a) {
     d2[a] = d[order[a]];
     for (int k = 0; k < m; ++k) Z2[static_cast<size_t>(k) * m + a] = Z[static_cast<size_t>(k) * m + order[a]];
@@ -131,49 +138,63 @@ bool tridiag_eigen(int m, std::vector<double>& d, std::vector<double>& e, std::v
   return true;
 }
 
+}  // namespace
+
+bool tridiag_eigen(int m, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Z) {
+  return tridiag_ql<double>(m, d, e, Z);
+}
+
+// The decomposition is computed in extended precision (x86 80-bit long double, epsilon ~1e-19)
+// from the FP64 operator entries and rounded to FP64 at the end.  A QL sweep is accurate to
+// epsilon * lambda_max in absolute terms; on stretched grids lambda_max / lambda_1 reaches
+// ~2e5, so in FP64 the smallest eigenvalues (which dominate the solution for small sigma) and
+// their vectors carry relative errors near 1e-11.  The extended sweep brings them to the FP64
+// rounding of the exact decomposition of the FP64 operator.
 std::string eigen_1d(Axis1D& ax) {
+  using R = long double;
   const int m = ax.m;
-  std::vector<double> sv(m), d(m), e(m, 0.0), Q;
-  for (int i = 0; i < m; ++i) sv[i] = std::sqrt(ax.vol[i]);
-  for (int i = 0; i < m; ++i) d[i] = ax.k_diag[i] / ax.vol[i];
-  for (int i = 0; i + 1 < m; ++i) e[i] = ax.k_off[i] / (sv[i] * sv[i + 1]);
-  if (!tridiag_eigen(m, d, e, Q)) return "tridiagonal eigensolver did not converge";
+  std::vector<R> sv(m), d(m), e(m, R(0)), Q;
+  for (int i = 0; i < m; ++i) sv[i] = std::sqrt(static_cast<R>(ax.vol[i]));
+  for (int i = 0; i < m; ++i) d[i] = static_cast<R>(ax.k_diag[i]) / static_cast<R>(ax.vol[i]);
+  for (int i = 0; i + 1 < m; ++i) e[i] = static_cast<R>(ax.k_off[i]) / (sv[i] * sv[i + 1]);
+  if (!tridiag_ql<R>(m, d, e, Q)) return "tridiagonal eigensolver did not converge";
   // Neumann at both walls: the constant is an exact null vector of K, so the smallest
   // eigenpair is set exactly: lambda_0 = 0, q_0 = V^{1/2} 1 / ||V^{1/2} 1||; the other
   // vectors are re-orthogonalized against it.
   if (ax.null_mode) {
-    double nrm = 0.0;
-    for (int i = 0; i < m; ++i) nrm += ax.vol[i];
+    R nrm = 0;
+    for (int i = 0; i < m; ++i) nrm += static_cast<R>(ax.vol[i]);
     nrm = std::sqrt(nrm);
-    std::vector<double> q0(m);
-    double dot = 0.0;
+    std::vector<R> q0(m);
+    R dot = 0;
     for (int i = 0; i < m; ++i) {
       q0[i] = sv[i] / nrm;
       dot += q0[i] * Q[static_cast<size_t>(i) * m];
     }
-    const double sgn = dot >= 0.0 ? 1.0 : -1.0;
+    const R sgn = dot >= R(0) ? R(1) : R(-1);
     for (int i = 0; i < m; ++i) Q[static_cast<size_t>(i) * m] = sgn * q0[i];
-    d[0] = 0.0;
+    d[0] = R(0);
     for (int a = 1; a < m; ++a) {
-      double h = 0.0, nn = 0.0;
+      R h = 0, nn = 0;
       for (int i = 0; i < m; ++i) h += q0[i] * Q[static_cast<size_t>(i) * m + a];
       for (int i = 0; i < m; ++i) {
-        double& z = Q[static_cast<size_t>(i) * m + a];
+        R& z = Q[static_cast<size_t>(i) * m + a];
         z -= h * q0[i];
         nn += z * z;
       }
-      nn = 1.0 / std::sqrt(nn);
+      nn = R(1) / std::sqrt(nn);
       for (int i = 0; i < m; ++i) Q[static_cast<size_t>(i) * m + a] *= nn;
     }
   }
-  ax.lam = d;
+  ax.lam.resize(m);
+  for (int a = 0; a < m; ++a) ax.lam[a] = static_cast<double>(d[a]);
   ax.E.assign(static_cast<size_t>(m) * m, 0.0);
   ax.Einv.assign(static_cast<size_t>(m) * m, 0.0);
   for (int i = 0; i < m; ++i)
     for (int a = 0; a < m; ++a) {
-      const double q = Q[static_cast<size_t>(i) * m + a];
-      ax.E[static_cast<size_t>(i) * m + a] = q / sv[i];
-      ax.Einv[static_cast<size_t>(a) * m + i] = q * sv[i];
+      const R q = Q[static_cast<size_t>(i) * m + a];
+      ax.E[static_cast<size_t>(i) * m + a] = static_cast<double>(q / sv[i]);
+      ax.Einv[static_cast<size_t>(a) * m + i] = static_cast<double>(q * sv[i]);
     }
   return "";
 }
