@@ -110,7 +110,9 @@ def test_pressure_192x160x224_mixed(torch):
     prob, f = workloads.workload_pressure()
     g = _golden("c4_pressure")
     fd = torch.from_numpy(f).cuda()
-    for precision, tol in (("fp64", 1e-11), ("bf16_ir", 1e-10), ("bf16x3_ir", 1e-10)):
+    # FP64 at the 1e-12 target (the two independent oracles differ by 6.1e-13 here, see
+    # tests/golden/oracle_floor.json)
+    for precision, tol in (("fp64", 1e-12), ("bf16_ir", 1e-10), ("bf16x3_ir", 1e-10)):
         plan = Plan(prob.faces, pressure=True, precision=precision)
         u = plan.solve(fd)
         torch.cuda.synchronize()

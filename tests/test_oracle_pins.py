@@ -355,3 +355,17 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         return orig_h(faces_, -sigma_, *a, **k)
     monkeypatch.setattr(fv, "helmholtz_matrix", wrong_sign)
     assert err() > 1e-3
+
+
+def test_oracle_floor_recorded():
+    """The mutual difference of two independent FP64 oracles (tests/golden/oracle_floor.json,
+    written by make_oracle_samples.py --floor) lies under every FP64 parity tolerance (1e-12)
+    for each full-size configuration, so those tolerances test the solver, not the oracle."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_floor.json")
+    data = json.load(open(path))
+    for name in ("c1", "c2_tau0.001", "c2_tau1", "c2_tau100", "c3", "c4_pressure"):
+        assert name in data, name
+        for row in data[name]["rhs"]:
+            assert row["rel_inf"] <= 1e-12, (name, row)
