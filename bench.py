@@ -329,6 +329,7 @@ def run_serving(torch, args):
         times = np.cumsum(rng.exponential(1.0 / rate, n_meas))
         idx = list(range(n_warm, n_warm + n_meas))
         recs = stream(srv, idx, times)
+        stats = srv.stats()
         srv.close()
         bad = [r for r in recs if r["status"] != 0]
         lat = np.array([r["t_done"] - r["t_submit"] for r in recs])
@@ -339,7 +340,10 @@ def run_serving(torch, args):
         out[prec] = dict(requests=len(recs), failed=len(bad), offered_rate_hz=rate, closed_loop_rate_hz=cap,
                          pts_per_s=pts / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
                          p99_ms=float(np.percentile(lat, 99) * 1e3), mean_queue_ms=float(wait.mean() * 1e3),
-                         mean_sweeps=float(np.mean([r["sweeps"] for r in recs])))
+                         mean_sweeps=float(np.mean([r["sweeps"] for r in recs])),
+                         plan_hit_rate=stats["plan_hits"] / max(1, stats["plan_hits"] + stats["plan_misses"]),
+                         plans_built=stats["plan_misses"],
+                         plan_setup_ms_mean=1e3 * stats["setup_seconds"] / max(1, stats["plan_misses"]))
         log(f"[serve] {prec}: {out[prec]}")
     best = max(out, key=lambda k: out[k]["pts_per_s"])
     line = dict(metric="grid-pts/s per Helmholtz solve @1e-10 rel err (serving stream); p50/p99 latency",

@@ -244,7 +244,17 @@ helm_status helm_server_poll(helm_server* s, helm_request_record* out, int max, 
 helm_status helm_server_drain(helm_server* s);
 /* Current time on the server clock (seconds since creation). */
 double helm_server_now(const helm_server* s);
-/* Drains, stops the threads and releases the server (cached plans stay until process exit). */
+/* Counters since creation: requests submitted and completed; plan lookups that found a resident
+ * plan (hits) or built one (misses: host eigen-decomposition and upload, done inside submit), and
+ * the seconds spent building them. */
+typedef struct {
+  long long submitted, completed, plan_hits, plan_misses;
+  double setup_seconds;
+} helm_server_stats_t;
+helm_status helm_server_stats(helm_server* s, helm_server_stats_t* out);
+/* Drains, stops the threads and releases the server and its resident plans.  A server keeps at
+ * most 2048 resident plans (least recently used evicted; an evicted plan lives until its queued
+ * and running requests complete); the 1D eigenbases are shared across plans per axis. */
 void helm_server_destroy(helm_server* s);
 
 /* Host-only simulation of the admission policy on a virtual clock (no device): n requests

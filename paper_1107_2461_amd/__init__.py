@@ -322,6 +322,13 @@ class Server:
     def now(self):
         return load().helm_server_now(self._h)
 
+    def stats(self):
+        """Counters since creation (helm_server_stats): submitted, completed, plan_hits,
+        plan_misses, setup_seconds."""
+        st = _lib.HelmServerStats()
+        check(load().helm_server_stats(self._h, C.byref(st)), "helm_server_stats")
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().helm_server_destroy(self._h)

@@ -45,6 +45,11 @@ class HelmRequestRecord(C.Structure):
                 ("slot", C.c_int)]
 
 
+class HelmServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_longlong), ("completed", C.c_longlong), ("plan_hits", C.c_longlong),
+                ("plan_misses", C.c_longlong), ("setup_seconds", C.c_double)]
+
+
 P = C.c_void_p
 DP = C.POINTER(C.c_double)
 IP = C.POINTER(C.c_int)
@@ -76,6 +81,7 @@ SIGNATURES = {
     "helm_server_poll": (C.c_int, [P, C.POINTER(HelmRequestRecord), C.c_int, IP, C.c_int]),
     "helm_server_drain": (C.c_int, [P]),
     "helm_server_now": (C.c_double, [P]),
+    "helm_server_stats": (C.c_int, [P, C.POINTER(HelmServerStats)]),
     "helm_server_destroy": (None, [P]),
     "helm_sched_simulate": (C.c_int, [C.c_int, DP, DP, C.POINTER(C.c_size_t), C.c_int, C.c_size_t, C.c_double, DP,
                                       DP]),

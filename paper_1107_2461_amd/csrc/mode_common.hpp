@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   using vec_t = typename T::vec_t;
   constexpr int WN = 4 / W;
   constexpr int NT = WN * NB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % W, wn = wave / W;
   const int l16 = lane & 15, g = lane >> 4;
   const long long total = S * Nn;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256, MINB) void k_right(const TC* __restrict__ Msw,
   using vec_t = typename T::vec_t;
   constexpr int WM = 4 / W;
   constexpr int MT = WM * MB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wn = wave % W, wm = wave / W;
   const int l16 = lane & 15, g = lane >> 4;
   const long long mwg = static_cast<long long>(blockIdx.x) * MT;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void k_left_bf16(const bf16_t* __restrict__ Ms
                                                    long long Nn, EpiArgs ep) {
   constexpr int WN = 4 / W;
   constexpr int NT = WN * NB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % W, wn = wave / W;
   const int l16 = lane & 15, g = lane >> 4;
   const long long total = S * Nn;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void k_right_bf16(const bf16_t* __restrict__ M
                                                     long long Mrows, EpiArgs ep) {
   constexpr int WM = 4 / W;
   constexpr int MT = WM * MB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wn = wave % W, wm = wave / W;
   const int l16 = lane & 15, g = lane >> 4;
   const long long mwg = static_cast<long long>(blockIdx.x) * MT;

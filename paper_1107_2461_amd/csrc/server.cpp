@@ -44,9 +44,22 @@ int pick_next(const Q& queue, int free_slots, size_t used, size_t budget, double
   return -1;
 }
 
+// Plans are shared between the resident map and the requests that use them; the last owner
+// destroys the plan (an evicted plan stays alive until its queued and running requests finish).
+using PlanRef = std::shared_ptr<helm_plan>;
+inline PlanRef adopt(helm_plan* p) { return PlanRef(p, [](helm_plan* q) { helm_destroy(q); }); }
+
+// Resident plans kept per server (least recently used evicted beyond this).  A plan owns no
+// large memory of its own: its 1D eigenbases are shared through the per-axis cache and a split-
+// BF16 plan's lambda_x + lambda_y table through the per-axis-pair cache, both alive while some
+// plan uses them.  The bound is large so that the axes of a workload stay referenced (an
+// evicted axis is rebuilt by the extended-precision eigensolver) and small enough that the
+// pair tables stay within a few hundred MB.
+constexpr size_t kMaxResidentPlans = 2048;
+
 struct Request {
   long long id = 0;
-  helm_plan* plan = nullptr;
+  PlanRef plan;
   std::vector<double> sigma;
   int nrhs = 0;
   const double* f = nullptr;
@@ -81,7 +94,14 @@ struct helm_server {
   long long submitted = 0, completed = 0;
   bool stop = false;
   std::mutex plan_mu;
-  std::map<std::string, helm_plan*> plans;
+  struct Resident {
+    PlanRef plan;
+    unsigned long long last_use = 0;
+  };
+  std::map<std::string, Resident> plans;
+  unsigned long long use_clock = 0;
+  long long plan_hits = 0, plan_misses = 0;  // guarded by plan_mu
+  double setup_seconds = 0.0;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -138,7 +158,7 @@ struct helm_server {
         else
           st = HELM_ENOMEM;
       }
-      if (st == HELM_OK) st = helm_solve(r.plan, r.f, r.u, r.nrhs, r.sigma.data(), s.ws, s.stream, &info);
+      if (st == HELM_OK) st = helm_solve(r.plan.get(), r.f, r.u, r.nrhs, r.sigma.data(), s.ws, s.stream, &info);
       if (st == HELM_OK && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
       helm_request_record rec{};
       rec.id = r.id;
@@ -204,17 +224,30 @@ extern "C" helm_status helm_server_submit(helm_server* s, const helm_grid* grid,
                                           int nrhs, const double* f, double* u, long long id) {
   if (!s || !grid || !bc || !sigma || !f || !u || nrhs < 1 || nrhs > 64) return HELM_EINVAL;
   const double t_submit = s->now();
-  helm_plan* plan = nullptr;
+  PlanRef plan;
   {
     std::lock_guard<std::mutex> lk(s->plan_mu);
     const std::string key = plan_key(grid, bc);
     auto it = s->plans.find(key);
     if (it != s->plans.end()) {
-      plan = it->second;
+      plan = it->second.plan;
+      it->second.last_use = ++s->use_clock;
+      ++s->plan_hits;
     } else {
-      const helm_status st = helm_setup(grid, bc, 0.0, &s->opts, &plan);
+      const auto t_setup = std::chrono::steady_clock::now();
+      helm_plan* raw = nullptr;
+      const helm_status st = helm_setup(grid, bc, 0.0, &s->opts, &raw);
       if (st != HELM_OK) return st;
-      s->plans[key] = plan;
+      plan = adopt(raw);
+      if (s->plans.size() >= kMaxResidentPlans) {
+        auto lru = s->plans.begin();
+        for (auto jt = s->plans.begin(); jt != s->plans.end(); ++jt)
+          if (jt->second.last_use < lru->second.last_use) lru = jt;
+        s->plans.erase(lru);
+      }
+      s->plans[key] = helm_server::Resident{plan, ++s->use_clock};
+      ++s->plan_misses;
+      s->setup_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_setup).count();
     }
   }
   auto r = std::make_unique<Request>();
@@ -225,7 +258,7 @@ extern "C" helm_status helm_server_submit(helm_server* s, const helm_grid* grid,
   r->f = f;
   r->u = u;
   r->t_submit = t_submit;
-  helm_status st = helm_workspace_size(plan, nrhs, &r->foot);
+  helm_status st = helm_workspace_size(plan.get(), nrhs, &r->foot);
   if (st != HELM_OK) return st;
   if (r->foot > s->budget) return HELM_EINVAL;
   {
@@ -251,6 +284,20 @@ extern "C" helm_status helm_server_poll(helm_server* s, helm_request_record* out
   return HELM_OK;
 }
 
+extern "C" helm_status helm_server_stats(helm_server* s, helm_server_stats_t* out) {
+  if (!s || !out) return HELM_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+  }
+  std::lock_guard<std::mutex> lk(s->plan_mu);
+  out->plan_hits = s->plan_hits;
+  out->plan_misses = s->plan_misses;
+  out->setup_seconds = s->setup_seconds;
+  return HELM_OK;
+}
+
 extern "C" helm_status helm_server_drain(helm_server* s) {
   if (!s) return HELM_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -273,7 +320,7 @@ extern "C" void helm_server_destroy(helm_server* s) {
     if (sl->ws) (void)hipFree(sl->ws);
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
   }
-  for (auto& kv : s->plans) helm_destroy(kv.second);
+  s->plans.clear();
   delete s;
 }
 

@@ -30,6 +30,7 @@ namespace {
 // reference-counted cache keyed by the axis definition (faces, location, walls, device).
 struct DevAxis {
   Axis1D host;
+  std::string key;           // cache key (faces, location, walls, device)
   int device = 0;
   double* lam = nullptr;     // m eigenvalues
   double* coef = nullptr;    // 3m: lower, diag, upper rows of A
@@ -57,6 +58,12 @@ struct DevAxis {
 
 std::mutex g_cache_mu;
 std::map<std::string, std::weak_ptr<DevAxis>> g_cache;
+
+// Drops the entries of a weak cache whose object is gone (keys hold whole face arrays).
+template <typename T>
+void purge_expired(std::map<std::string, std::weak_ptr<T>>& m) {
+  for (auto it = m.begin(); it != m.end();) it = it->second.expired() ? m.erase(it) : std::next(it);
+}
 
 helm_status from_hip(hipError_t e) {
   if (e == hipSuccess) return HELM_OK;
@@ -95,6 +102,7 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
   }
   auto ax = std::make_shared<DevAxis>();
   ax->device = dev;
+  ax->key = key;
   Axis1D& h = ax->host;
   if (!build_operator_1d(n, faces, loc, lo, hi, h).empty()) return HELM_EINVAL;
   if (h.m > 512) return HELM_EINVAL;
@@ -142,6 +150,7 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
         return HELM_OK;
       }
     }
+    if (g_cache.size() >= 1024) purge_expired(g_cache);
     g_cache[key] = ax;
   }
   out = ax;
@@ -149,6 +158,77 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device buffer freed (on its device) with its last owner.
+struct DevBuf {
+  double* p = nullptr;
+  int device = 0;
+  ~DevBuf() {
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    (void)hipFree(p);
+    (void)hipSetDevice(cur);
+  }
+};
+
+// lambda_x[a] + lambda_y[b] per (x axis, y axis) pair, summed in FP64 and shared by every plan
+// on that pair (the per-(a, b) part of the eq. 26-27 denominator for split-BF16 solves), so
+// that building or dropping a plan on cached axes touches no device memory.
+std::mutex g_pair_mu;
+std::map<std::string, std::weak_ptr<DevBuf>> g_pair_cache;
+
+helm_status get_lamxy(const DevAxis& X, const DevAxis& Y, std::shared_ptr<DevBuf>& out) {
+  const std::string key = X.key + "|" + Y.key;
+  std::lock_guard<std::mutex> lk(g_pair_mu);
+  auto it = g_pair_cache.find(key);
+  if (it != g_pair_cache.end() && (out = it->second.lock())) return HELM_OK;
+  const int mx = X.host.m, my = Y.host.m;
+  std::vector<double> t(static_cast<size_t>(mx) * my);
+  for (int b = 0; b < my; ++b)
+    for (int a = 0; a < mx; ++a) t[static_cast<size_t>(b) * mx + a] = X.host.lam[a] + Y.host.lam[b];
+  auto buf = std::make_shared<DevBuf>();
+  buf->device = X.device;
+  const hipError_t e = upload(&buf->p, t.data(), t.size());
+  if (e != hipSuccess) return from_hip(e);
+  if (g_pair_cache.size() >= 1024) purge_expired(g_pair_cache);
+  g_pair_cache[key] = buf;
+  out = buf;
+  return HELM_OK;
+}
+
+// Pinned host buffers for the refinement norms (2 * kMaxRhs * kNormStripes words each), taken
+// by a solve for its duration and returned: the pool grows to the peak number of concurrent
+// refined solves and lives until process exit (pinned allocation and release synchronize the
+// device, so they stay off the solve path).
+std::mutex g_pin_mu;
+std::vector<unsigned long long*> g_pin_pool;
+
+unsigned long long* take_pinned_norms() {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin_pool.empty()) {
+      unsigned long long* b = g_pin_pool.back();
+      g_pin_pool.pop_back();
+      return b;
+    }
+  }
+  unsigned long long* b = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b), 2 * kMaxRhs * kNormStripes * sizeof(unsigned long long)) !=
+      hipSuccess)
+    return nullptr;
+  return b;
+}
+void give_pinned_norms(unsigned long long* b) {
+  if (!b) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_pool.push_back(b);
+}
+struct PinnedNorms {
+  unsigned long long* p = take_pinned_norms();
+  ~PinnedNorms() { give_pinned_norms(p); }
+};
 
 }  // namespace
 
@@ -187,20 +267,8 @@ struct helm_plan {
   helm_opts opts{};
   bool all_neumann = false;
   int device = 0;
-  unsigned long long* host_norms = nullptr;  // pinned, 2 * kMaxRhs * kNormStripes
-  double* lamxy = nullptr;                   // device, m[0] * m[1]: lamx[a] + lamy[b] (split-BF16)
-  std::mutex mu;                             // guards host_norms
+  std::shared_ptr<DevBuf> lamxy;             // m[0] * m[1]: lamx[a] + lamy[b] (split-BF16), shared
   mutable StageProfiler prof;
-  ~helm_plan() {
-    if (host_norms) (void)hipHostFree(host_norms);
-    if (lamxy) {
-      int cur = 0;
-      (void)hipGetDevice(&cur);
-      (void)hipSetDevice(device);
-      (void)hipFree(lamxy);
-      (void)hipSetDevice(cur);
-    }
-  }
   long long npts() const { return static_cast<long long>(m[0]) * m[1] * m[2]; }
   bool refined() const {
     return opts.precision == HELM_FP32_IR || opts.precision == HELM_BF16_IR || opts.precision == HELM_BF16X3_IR;
@@ -315,18 +383,9 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
   }
   p->all_neumann = alln;
   if (has_zero_denominator(p.get(), sigma)) return HELM_ESINGULAR;
-  if (hipHostMalloc(reinterpret_cast<void**>(&p->host_norms),
-                    2 * kMaxRhs * kNormStripes * sizeof(unsigned long long)) != hipSuccess)
-    return HELM_ENOMEM;
   if (p->prec() == P_BF16X3) {
-    // per-(a, b) part of the eq. 26-27 denominator, summed in FP64 once per plan
-    const std::vector<double>& lx = p->ax[0]->host.lam;
-    const std::vector<double>& ly = p->ax[1]->host.lam;
-    std::vector<double> t(static_cast<size_t>(p->m[0]) * p->m[1]);
-    for (int b = 0; b < p->m[1]; ++b)
-      for (int a = 0; a < p->m[0]; ++a) t[static_cast<size_t>(b) * p->m[0] + a] = lx[a] + ly[b];
-    const hipError_t e = upload(&p->lamxy, t.data(), t.size());
-    if (e != hipSuccess) return from_hip(e);
+    const helm_status s = get_lamxy(*p->ax[0], *p->ax[1], p->lamxy);
+    if (s != HELM_OK) return s;
   }
   *out = p.release();
   return HELM_OK;
@@ -429,7 +488,7 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   ep.lamx = X.lam;
   ep.lamy = Y.lam;
   ep.lamz = Z.lam;
-  ep.lamxy = p->lamxy;
+  ep.lamxy = p->lamxy ? p->lamxy->p : nullptr;
   ep.nx = static_cast<int>(nx);
   ep.eq28 = p->opts.null_mode == HELM_NULL_PAPER_EQ28;
   ep.norms = norms;
@@ -660,7 +719,8 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   }
   if (e != hipSuccess) return from_hip(e);
   if (!p->refined()) return from_hip(project_null());
-  std::lock_guard<std::mutex> lk(p->mu);
+  PinnedNorms hn;  // pinned host copy of the norm stripes, from a process-wide pool
+  if (!hn.p) return HELM_ENOMEM;
   int sweeps = 1;
   double last = 0.0, prev = 1.0;  // the first solve's "correction" is u itself
   bool conv = false;
@@ -669,7 +729,7 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
     if (e == hipSuccess) e = timed(p, HELM_STAGE_RESIDUAL, st, [&] { return stencil(1, u, f, L1, store, sa, st); });
     if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(p->host_norms, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
+      e = hipMemcpyAsync(hn.p, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return from_hip(e);
@@ -680,8 +740,8 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
       // the stripes hold non-negative FP64 bit patterns (NaN as the largest): integer max
       unsigned long long bd = 0, bu = 0;
       for (int q = 0; q < kNormStripes; ++q) {
-        bd = std::max(bd, p->host_norms[(2 * r) * kNormStripes + q]);
-        bu = std::max(bu, p->host_norms[(2 * r + 1) * kNormStripes + q]);
+        bd = std::max(bd, hn.p[(2 * r) * kNormStripes + q]);
+        bu = std::max(bu, hn.p[(2 * r + 1) * kNormStripes + q]);
       }
       double dm, um;
       std::memcpy(&dm, &bd, 8);

@@ -5,6 +5,7 @@ on the same data: bitwise equality is expected, and at worst the solver toleranc
 device-workspace budget is respected at every instant; requests overlap in time when the
 budget and slots allow it, and are serialised when the budget admits only one at a time.
 """
+import numpy as np
 import pytest
 
 import workloads
@@ -124,3 +125,51 @@ def test_submit_rejects_request_larger_than_budget(torch):
     with pytest.raises(HelmError, match="EINVAL"):
         srv.submit(1, prob.faces, f, torch.empty_like(f), [1.0])
     srv.close()
+
+
+def test_plan_cache_counters(torch):
+    """Every submit is one plan lookup: a miss builds the plan (counted with its setup time),
+    and repeats of a grid/wall combination hit the resident plan."""
+    from paper_1107_2461_amd import Server
+    reqs = _requests(torch, 12, seed=8)
+    keys = {(tuple(np.round(np.concatenate(prob.faces), 15)), tuple(prob.bc_lo), tuple(prob.bc_hi))
+            for _, prob, _ in reqs}
+    srv = Server(1 << 30, slots=2)
+    for _ in range(2):
+        for r, prob, f in reqs:
+            srv.submit(r["rid"], prob.faces, f, torch.empty_like(f), [prob.sigma] * f.shape[0], prob.bc_lo,
+                       prob.bc_hi)
+        srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert st["submitted"] == st["completed"] == 2 * len(reqs)
+    assert st["plan_hits"] + st["plan_misses"] == 2 * len(reqs)
+    assert st["plan_misses"] == len(keys)
+    assert st["setup_seconds"] > 0.0
+
+
+def test_resident_plans_bounded_lru(torch):
+    """Beyond 2048 resident plans the least recently used is evicted: after 2100 distinct grids,
+    the first grid misses again (rebuilt) while the most recent one hits."""
+    from paper_1107_2461_amd import Server
+    n = 8
+    f = torch.randn((1, n, n, n), device="cuda", dtype=torch.float64)
+    N = 2100
+    grids = [tuple(workloads.stretched_faces(n, 1.0 + 0.0004 * k) for _ in range(3)) for k in range(N)]
+    srv = Server(1 << 30, slots=2)
+    outs = []
+    for k, faces in enumerate(grids):
+        u = torch.empty_like(f)
+        outs.append(u)
+        srv.submit(k, faces, f, u, [1.0])
+    srv.drain()
+    st = srv.stats()
+    assert st["plan_misses"] == N and st["plan_hits"] == 0
+    srv.submit(1000, grids[-1], f, torch.empty_like(f), [1.0])    # resident
+    srv.submit(1001, grids[0], f, torch.empty_like(f), [1.0])     # evicted long ago
+    srv.drain()
+    recs = srv.poll(max_records=N + 8)
+    st = srv.stats()
+    srv.close()
+    assert st["plan_hits"] == 1 and st["plan_misses"] == N + 1
+    assert len(recs) == N + 2 and all(r["status"] == 0 for r in recs)
