@@ -364,8 +364,8 @@ hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec t
   const int rows = (4 / wx) * kStencilJS;  // y rows per workgroup
   const int nby = (a.ny + rows - 1) / rows;
   const long long xy_blocks = static_cast<long long>(nbx) * nby * a.nrhs;
-  // z-chunks: enough workgroups to fill the chip (about 2048), chunks of at least 4 planes
-  int nzc = static_cast<int>(std::max<long long>(1, std::min<long long>((a.nz + 3) / 4, (2048 + xy_blocks - 1) / xy_blocks)));
+  // z-chunks: enough workgroups to fill the chip (about 4096), chunks of at least 4 planes
+  int nzc = static_cast<int>(std::max<long long>(1, std::min<long long>((a.nz + 3) / 4, (4096 + xy_blocks - 1) / xy_blocks)));
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
   const long long tiles = xy_blocks * nzc;

@@ -201,11 +201,20 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const long long o = min(mq + t, Mrows - 1) - r_lo * PQ;
+        if constexpr (VEC) {
+          // the lane's four rows are four consecutive, aligned pq of one RHS: one 32-byte load
+          const long long o = (mq < Mrows ? mq : 0) - (mq < Mrows ? r_lo * PQ : 0);
           const bool nxt = o >= PQ;
-          shift[mb][t] = static_cast<float>(ep.lamxy[nxt ? o - PQ : o] + (nxt ? sg1 : sg0));
+          const d4v l4 = *reinterpret_cast<const d4v*>(ep.lamxy + (nxt ? o - PQ : o));
+#pragma unroll
+          for (int t = 0; t < 4; ++t) shift[mb][t] = static_cast<float>(l4[t] + (nxt ? sg1 : sg0));
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const long long o = min(mq + t, Mrows - 1) - r_lo * PQ;
+            const bool nxt = o >= PQ;
+            shift[mb][t] = static_cast<float>(ep.lamxy[nxt ? o - PQ : o] + (nxt ? sg1 : sg0));
+          }
         }
       }
     } else {
