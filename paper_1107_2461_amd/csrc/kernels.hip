@@ -123,8 +123,12 @@ hipError_t mode_right(Prec p, const void* Msw, int K, const void* X, Prec tin, v
 // ------------------------------------------------------------------ Thomas along z
 // One lane per (r, b, a) line; at step k a wavefront touches 64 consecutive a of one
 // z-plane (coalesced).  Forward elimination keeps only a checkpoint of (pivot, rhs) every
-// SEG steps; the backward sweep recomputes one segment at a time into registers, so the
-// line is read twice and written once (24 B/point) and can be updated in place.
+// kSeg steps; the backward sweep recomputes one segment at a time into registers, so the
+// line is read twice and written once (24 B/point) and can be updated in place.  The kSeg
+// values of a segment are loaded together and the next segment's loads are issued before the
+// current one is eliminated, so a lane keeps up to 2 kSeg loads in flight.  Pivots are
+// inverted once (hardware reciprocal + two Newton steps, a few ulp; the systems are
+// diagonally dominant) and both sweeps multiply by the inverse.
 constexpr int kSeg = 16;
 
 size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs) {
@@ -132,7 +136,7 @@ size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs) {
   return static_cast<size_t>(2 * nseg) * nx * ny * nrhs * sizeof(double);
 }
 
-__global__ __launch_bounds__(256) void k_thomas(double* __restrict__ v, ThomasArgs a, double* __restrict__ chk) {
+__global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArgs a, double* __restrict__ chk) {
   const long long Nn = static_cast<long long>(a.nx) * a.ny;
   const long long nl = Nn * a.nrhs;
   const long long line = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -145,69 +149,107 @@ __global__ __launch_bounds__(256) void k_thomas(double* __restrict__ v, ThomasAr
   double* col = v + static_cast<long long>(r) * a.nz * Nn + n;
   const int nz = a.nz;
   const int nseg = (nz + kSeg - 1) / kSeg;
-  // forward sweep: beta_k = D_k - m_k Koff_{k-1}, y_k = V_k g_k - m_k y_{k-1}
-  double beta = 0.0, y = 0.0;
-  for (int k = 0; k < nz; ++k) {
-    const double d = a.kdiag[k] + c * a.vol[k];
-    const double rhs = a.vol[k] * col[static_cast<long long>(k) * Nn];
-    if (k == 0) {
-      beta = d;
-      y = rhs;
-    } else {
-      const double m = a.koff[k - 1] / beta;
-      beta = d - m * a.koff[k - 1];
-      y = rhs - m * y;
+  auto load_seg = [&](int j, double (&g)[kSeg]) {
+#pragma unroll
+    for (int t = 0; t < kSeg; ++t) {
+      const int k = j * kSeg + t;
+      g[t] = k < nz ? col[static_cast<long long>(k) * Nn] : 0.0;
     }
-    if ((k + 1) % kSeg == 0 && k + 1 < nz) {
-      const int sgi = (k + 1) / kSeg - 1;
-      chk[(2LL * sgi) * nl + line] = beta;
-      chk[(2LL * sgi + 1) * nl + line] = y;
-    }
-  }
-  // backward sweep, one segment at a time from the top
-  double vnext = 0.0;
-  for (int j = nseg - 1; j >= 0; --j) {
-    const int k0 = j * kSeg;
-    double bs[kSeg], ys[kSeg];
-    if (j > 0) {
-      beta = chk[(2LL * (j - 1)) * nl + line];
-      y = chk[(2LL * (j - 1) + 1) * nl + line];
+  };
+  // elimination of one segment from the carried (1 / beta, y): fills ib[t] = 1 / beta_k and
+  // ys[t] = y_k, with beta_k = D_k - Koff_{k-1}^2 / beta_{k-1}, y_k = V_k g_k - m_k y_{k-1}.
+  // The segment's operator entries are read and the diagonals and right-hand sides formed
+  // before the recurrence, so no load sits inside its dependent chain.
+  auto eliminate = [&](int j, const double (&g)[kSeg], double& ibeta, double& y, double (&ib)[kSeg],
+                       double (&ys)[kSeg]) {
+    double dg[kSeg], rh[kSeg], ko[kSeg];
+#pragma unroll
+    for (int t = 0; t < kSeg; ++t) {
+      const int k = min(j * kSeg + t, nz - 1);
+      const double vk = a.vol[k];
+      dg[t] = a.kdiag[k] + c * vk;
+      rh[t] = vk * g[t];
+      ko[t] = a.koff[max(k - 1, 0)];
     }
 #pragma unroll
     for (int t = 0; t < kSeg; ++t) {
-      const int k = k0 + t;
+      const int k = j * kSeg + t;
       if (k < nz) {
-        const double d = a.kdiag[k] + c * a.vol[k];
-        const double rhs = a.vol[k] * col[static_cast<long long>(k) * Nn];
         if (k == 0) {
-          beta = d;
-          y = rhs;
+          ibeta = recip(dg[t]);
+          y = rh[t];
         } else {
-          const double m = a.koff[k - 1] / beta;
-          beta = d - m * a.koff[k - 1];
-          y = rhs - m * y;
+          const double m = ko[t] * ibeta;
+          ibeta = recip(dg[t] - m * ko[t]);
+          y = rh[t] - m * y;
         }
       }
-      bs[t] = beta;
+      ib[t] = ibeta;
       ys[t] = y;
     }
+  };
+  double g0[kSeg], g1[kSeg], ib[kSeg], ys[kSeg];
+  double ibeta = 0.0, y = 0.0;
+  // forward sweep, checkpoints at the end of every segment but the last; the loop is unrolled
+  // by two so the two segment buffers swap roles without a copy (a copy would wait for the
+  // prefetch just issued)
+  auto fwd = [&](int j, const double (&cur)[kSeg], double (&nxt)[kSeg]) {
+    if (j + 1 < nseg) load_seg(j + 1, nxt);
+    eliminate(j, cur, ibeta, y, ib, ys);
+    if (j + 1 < nseg) {
+      chk[(2LL * j) * nl + line] = ibeta;
+      chk[(2LL * j + 1) * nl + line] = y;
+    }
+  };
+  load_seg(0, g0);
+  for (int j = 0; j < nseg; j += 2) {
+    fwd(j, g0, g1);
+    if (j + 1 < nseg) fwd(j + 1, g1, g0);
+  }
+  // backward sweep, one segment at a time from the top.  The checkpoint a segment starts
+  // from is loaded one segment ahead, before that segment's values: loads retire in issue
+  // order, so the state is in registers when its segment is eliminated.
+  double vnext = 0.0;
+  double ib_in = 0.0, y_in = 0.0;  // state entering the segment being eliminated
+  auto load_chk = [&](int j, double& ibc, double& yc) {  // state entering segment j (j > 0)
+    ibc = chk[(2LL * (j - 1)) * nl + line];
+    yc = chk[(2LL * (j - 1) + 1) * nl + line];
+  };
+  auto bwd = [&](int j, const double (&cur)[kSeg], double (&nxt)[kSeg]) {
+    double ib_nx = 0.0, y_nx = 0.0;
+    if (j > 1) load_chk(j - 1, ib_nx, y_nx);
+    if (j > 0) load_seg(j - 1, nxt);
+    ibeta = ib_in;
+    y = y_in;
+    eliminate(j, cur, ibeta, y, ib, ys);
+    double kup[kSeg];
+#pragma unroll
+    for (int t = 0; t < kSeg; ++t) kup[t] = a.koff[min(j * kSeg + t, nz - 2 < 0 ? 0 : nz - 2)];
 #pragma unroll
     for (int t = kSeg - 1; t >= 0; --t) {
-      const int k = k0 + t;
+      const int k = j * kSeg + t;
       if (k < nz) {
-        const double vk = (k == nz - 1) ? ys[t] / bs[t] : (ys[t] - a.koff[k] * vnext) / bs[t];
+        const double vk = (k == nz - 1) ? ys[t] * ib[t] : (ys[t] - kup[t] * vnext) * ib[t];
         col[static_cast<long long>(k) * Nn] = vk;
         vnext = vk;
       }
     }
+    ib_in = ib_nx;
+    y_in = y_nx;
+  };
+  if (nseg > 1) load_chk(nseg - 1, ib_in, y_in);
+  load_seg(nseg - 1, g0);
+  for (int j = nseg - 1; j >= 0; j -= 2) {
+    bwd(j, g0, g1);
+    if (j - 1 >= 0) bwd(j - 1, g1, g0);
   }
 }
 
 hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st) {
   const long long nl = static_cast<long long>(a.nx) * a.ny * a.nrhs;
   if (nl == 0) return hipSuccess;
-  const long long blocks = (nl + 255) / 256;
-  hipLaunchKernelGGL(k_thomas, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, v, a, static_cast<double*>(chk));
+  const long long blocks = (nl + 63) / 64;
+  hipLaunchKernelGGL(k_thomas, dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, v, a, static_cast<double*>(chk));
   return hipGetLastError();
 }
 
@@ -246,9 +288,6 @@ hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const d
 }
 
 // ------------------------------------------------------------------ 7-point operator / residual
-// A block of 64 x 4 lanes owns a 64 x 4 patch of (x, y) lines and marches along z through a
-// chunk of planes, carrying u(k-1), u(k), u(k+1) in registers, so u and f stream through
-// once; x and y neighbours come from the lanes next door (L1) or the adjacent patch (L2).
 // Column segments: a lane owns one x index and kStencilJS consecutive y rows and marches up a
 // z-chunk, keeping the rows of planes k-1, k (with the two y-halo rows) and k+1 in registers.
 // The x neighbours come from the adjacent lanes (cross-lane shuffle); only the two edge lanes
