@@ -121,67 +121,99 @@ hipError_t mode_right(Prec p, const void* Msw, int K, const void* X, Prec tin, v
 }
 
 // ------------------------------------------------------------------ Thomas along z
-// One lane per (r, b, a) line; at step k a wavefront touches 64 consecutive a of one
-// z-plane (coalesced).  Forward elimination keeps only a checkpoint of (pivot, rhs) every
-// kSeg steps; the backward sweep recomputes one segment at a time into registers, so the
-// line is read twice and written once (24 B/point) and can be updated in place.  The kSeg
-// values of a segment are loaded together and the next segment's loads are issued before the
-// current one is eliminated, so a lane keeps up to 2 kSeg loads in flight.  Pivots are
-// inverted once (hardware reciprocal + two Newton steps, a few ulp; the systems are
-// diagonally dominant) and both sweeps multiply by the inverse.
+// Two lanes per (r, b, a) line, in a two-sided (twisted) factorisation: lanes 0-31 of a wave
+// eliminate 32 consecutive lines downward from the first plane, lanes 32-63 eliminate the same
+// lines upward from the last plane.  Each half stops next to the middle row m = nz / 2, the
+// halves trade their last inverse pivot and right-hand side with one cross-half shuffle, both
+// solve row m, and each back-substitutes outward.  This halves the dependent chain of a line
+// and doubles the lanes working on it; at each step a half-wave touches 32 consecutive lines of
+// one z-plane (256 B).  Forward elimination keeps only a checkpoint of (1 / pivot, rhs) every
+// kSeg steps; the backward sweep recomputes one segment at a time into registers, so a line is
+// read twice and written once (24 B/point), in place.  The kSeg values of a segment are loaded
+// together and the next segment's loads are issued before the current one is eliminated.
+// Pivots are inverted once (hardware reciprocal + two Newton steps, a few ulp; the systems are
+// diagonally dominant) and both sweeps multiply by the inverse.  The z operator's rows are
+// staged in LDS once per workgroup.
 constexpr int kSeg = 16;
 
+namespace {
+long long thomas_lanes(long long nl) { return (nl + 31) / 32 * 64; }
+int thomas_nseg(int nz) { return (nz / 2 + kSeg - 1) / kSeg; }
+}  // namespace
+
 size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs) {
-  const long long nseg = (nz + kSeg - 1) / kSeg;
-  return static_cast<size_t>(2 * nseg) * nx * ny * nrhs * sizeof(double);
+  const long long nl = static_cast<long long>(nx) * ny * nrhs;
+  return static_cast<size_t>(2LL * thomas_nseg(nz) * thomas_lanes(nl)) * sizeof(double);
 }
 
 __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArgs a, double* __restrict__ chk) {
+  extern __shared__ double zrow[];  // K_z diagonal [nz], V_z [nz], K_z off-diagonal [nz] (last = 0)
+  const int nz = a.nz;
+  double* sk = zrow;
+  double* sv = zrow + nz;
+  double* so = zrow + 2 * nz;
+  for (int i = threadIdx.x; i < nz; i += 64) {
+    sk[i] = a.kdiag[i];
+    sv[i] = a.vol[i];
+    so[i] = i < nz - 1 ? a.koff[i] : 0.0;
+  }
+  __syncthreads();
   const long long Nn = static_cast<long long>(a.nx) * a.ny;
   const long long nl = Nn * a.nrhs;
-  const long long line = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int bot = threadIdx.x >> 5;  // 0: from the first plane down; 1: from the last plane up
+  const long long line = static_cast<long long>(blockIdx.x) * 32 + (threadIdx.x & 31);
+  const long long lane_id = static_cast<long long>(blockIdx.x) * 64 + threadIdx.x;
+  const long long nlanes = static_cast<long long>(gridDim.x) * 64;
+  // both lanes of a line leave together, so the middle-row shuffle only reads live partners
   if (line >= nl) return;
   const int r = static_cast<int>(line / Nn);
   const long long n = line - r * Nn;
   if (a.skip_null && n == 0) return;
   const int ax = static_cast<int>(n % a.nx), by = static_cast<int>(n / a.nx);
   const double c = a.lamx[ax] + a.lamy[by] + a.sigma[r];
-  double* col = v + static_cast<long long>(r) * a.nz * Nn + n;
-  const int nz = a.nz;
-  const int nseg = (nz + kSeg - 1) / kSeg;
+  const int m = nz / 2;
+  const int len = bot ? nz - 1 - m : m;  // rows this lane eliminates: m above the middle, the rest below
+  const long long stride = bot ? -Nn : Nn;
+  double* col0 = v + static_cast<long long>(r) * nz * Nn + n;
+  double* base = bot ? col0 + static_cast<long long>(nz - 1) * Nn : col0;
+  const int nseg = (m + kSeg - 1) / kSeg;
+  // row of step s, and the LDS index of the off-diagonal entry joining steps s - 1 and s
+  auto row_of = [&](int s) { return min(max(bot ? nz - 1 - s : s, 0), nz - 1); };
+  auto cpl_of = [&](int s) { return min(max(bot ? nz - 1 - s : s - 1, 0), nz - 1); };
   auto load_seg = [&](int j, double (&g)[kSeg]) {
 #pragma unroll
     for (int t = 0; t < kSeg; ++t) {
-      const int k = j * kSeg + t;
-      g[t] = k < nz ? col[static_cast<long long>(k) * Nn] : 0.0;
+      const int s = j * kSeg + t;
+      g[t] = s < len ? base[s * stride] : 0.0;
     }
   };
-  // elimination of one segment from the carried (1 / beta, y): fills ib[t] = 1 / beta_k and
-  // ys[t] = y_k, with beta_k = D_k - Koff_{k-1}^2 / beta_{k-1}, y_k = V_k g_k - m_k y_{k-1}.
-  // The segment's operator entries are read and the diagonals and right-hand sides formed
-  // before the recurrence, so no load sits inside its dependent chain.
+  // elimination of one segment from the carried (1 / beta, y): fills ib[t] = 1 / beta_s and
+  // ys[t] = y_s, with beta_s = D_s - Koff_s^2 / beta_{s-1}, y_s = V_s g_s - m_s y_{s-1}.  The
+  // segment's operator entries are read and its diagonals and right-hand sides formed before
+  // the recurrence, so no load sits inside the dependent chain.
   auto eliminate = [&](int j, const double (&g)[kSeg], double& ibeta, double& y, double (&ib)[kSeg],
                        double (&ys)[kSeg]) {
     double dg[kSeg], rh[kSeg], ko[kSeg];
 #pragma unroll
     for (int t = 0; t < kSeg; ++t) {
-      const int k = min(j * kSeg + t, nz - 1);
-      const double vk = a.vol[k];
-      dg[t] = a.kdiag[k] + c * vk;
+      const int s = j * kSeg + t;
+      const int rw = row_of(s);
+      const double vk = sv[rw];
+      dg[t] = sk[rw] + c * vk;
       rh[t] = vk * g[t];
-      ko[t] = a.koff[max(k - 1, 0)];
+      ko[t] = so[cpl_of(s)];
     }
 #pragma unroll
     for (int t = 0; t < kSeg; ++t) {
-      const int k = j * kSeg + t;
-      if (k < nz) {
-        if (k == 0) {
+      const int s = j * kSeg + t;
+      if (s < len) {
+        if (s == 0) {
           ibeta = recip(dg[t]);
           y = rh[t];
         } else {
-          const double m = ko[t] * ibeta;
-          ibeta = recip(dg[t] - m * ko[t]);
-          y = rh[t] - m * y;
+          const double mu = ko[t] * ibeta;
+          ibeta = recip(dg[t] - mu * ko[t]);
+          y = rh[t] - mu * y;
         }
       }
       ib[t] = ibeta;
@@ -189,7 +221,7 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
     }
   };
   double g0[kSeg], g1[kSeg], ib[kSeg], ys[kSeg];
-  double ibeta = 0.0, y = 0.0;
+  double ibeta = 0.0, y = 0.0;  // stays 0 on a side with no rows
   // forward sweep, checkpoints at the end of every segment but the last; the loop is unrolled
   // by two so the two segment buffers swap roles without a copy (a copy would wait for the
   // prefetch just issued)
@@ -197,23 +229,33 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
     if (j + 1 < nseg) load_seg(j + 1, nxt);
     eliminate(j, cur, ibeta, y, ib, ys);
     if (j + 1 < nseg) {
-      chk[(2LL * j) * nl + line] = ibeta;
-      chk[(2LL * j + 1) * nl + line] = y;
+      chk[(2LL * j) * nlanes + lane_id] = ibeta;
+      chk[(2LL * j + 1) * nlanes + lane_id] = y;
     }
   };
-  load_seg(0, g0);
+  if (nseg > 0) load_seg(0, g0);
   for (int j = 0; j < nseg; j += 2) {
     fwd(j, g0, g1);
     if (j + 1 < nseg) fwd(j + 1, g1, g0);
   }
-  // backward sweep, one segment at a time from the top.  The checkpoint a segment starts
-  // from is loaded one segment ahead, before that segment's values: loads retire in issue
-  // order, so the state is in registers when its segment is eliminated.
-  double vnext = 0.0;
+  // the middle row, from both eliminated sides (computed in the same order by both lanes)
+  const double ib_p = __shfl_xor(ibeta, 32), y_p = __shfl_xor(y, 32);
+  const double ib_t = bot ? ib_p : ibeta, y_t = bot ? y_p : y;
+  const double ib_b = bot ? ibeta : ib_p, y_b = bot ? y : y_p;
+  const double o_t = so[max(m - 1, 0)], o_b = so[m];  // couplings of row m to rows m - 1 and m + 1
+  const double mt = o_t * ib_t, mb = o_b * ib_b;
+  const double vm = sv[m];
+  const double dm = sk[m] + c * vm - mt * o_t - mb * o_b;
+  const double xm = (vm * col0[static_cast<long long>(m) * Nn] - mt * y_t - mb * y_b) / dm;
+  if (!bot) col0[static_cast<long long>(m) * Nn] = xm;
+  // backward sweep, one segment at a time from the middle outward.  The checkpoint a segment
+  // starts from is loaded one segment ahead, before that segment's values: loads retire in
+  // issue order, so the state is in registers when its segment is eliminated.
+  double xnext = xm;
   double ib_in = 0.0, y_in = 0.0;  // state entering the segment being eliminated
   auto load_chk = [&](int j, double& ibc, double& yc) {  // state entering segment j (j > 0)
-    ibc = chk[(2LL * (j - 1)) * nl + line];
-    yc = chk[(2LL * (j - 1) + 1) * nl + line];
+    ibc = chk[(2LL * (j - 1)) * nlanes + lane_id];
+    yc = chk[(2LL * (j - 1) + 1) * nlanes + lane_id];
   };
   auto bwd = [&](int j, const double (&cur)[kSeg], double (&nxt)[kSeg]) {
     double ib_nx = 0.0, y_nx = 0.0;
@@ -222,23 +264,23 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
     ibeta = ib_in;
     y = y_in;
     eliminate(j, cur, ibeta, y, ib, ys);
-    double kup[kSeg];
+    double kup[kSeg];  // off-diagonal joining step s with step s + 1 (the middle row after the last)
 #pragma unroll
-    for (int t = 0; t < kSeg; ++t) kup[t] = a.koff[min(j * kSeg + t, nz - 2 < 0 ? 0 : nz - 2)];
+    for (int t = 0; t < kSeg; ++t) kup[t] = so[cpl_of(j * kSeg + t + 1)];
 #pragma unroll
     for (int t = kSeg - 1; t >= 0; --t) {
-      const int k = j * kSeg + t;
-      if (k < nz) {
-        const double vk = (k == nz - 1) ? ys[t] * ib[t] : (ys[t] - kup[t] * vnext) * ib[t];
-        col[static_cast<long long>(k) * Nn] = vk;
-        vnext = vk;
+      const int s = j * kSeg + t;
+      if (s < len) {
+        const double xs = (ys[t] - kup[t] * xnext) * ib[t];
+        base[s * stride] = xs;
+        xnext = xs;
       }
     }
     ib_in = ib_nx;
     y_in = y_nx;
   };
   if (nseg > 1) load_chk(nseg - 1, ib_in, y_in);
-  load_seg(nseg - 1, g0);
+  if (nseg > 0) load_seg(nseg - 1, g0);
   for (int j = nseg - 1; j >= 0; j -= 2) {
     bwd(j, g0, g1);
     if (j - 1 >= 0) bwd(j - 1, g1, g0);
@@ -248,8 +290,11 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
 hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st) {
   const long long nl = static_cast<long long>(a.nx) * a.ny * a.nrhs;
   if (nl == 0) return hipSuccess;
-  const long long blocks = (nl + 63) / 64;
-  hipLaunchKernelGGL(k_thomas, dim3(static_cast<unsigned>(blocks)), dim3(64), 0, st, v, a, static_cast<double*>(chk));
+  if (a.nz < 1 || a.nz > 2048) return hipErrorInvalidValue;
+  const long long blocks = thomas_lanes(nl) / 64;
+  const size_t lds = 3 * static_cast<size_t>(a.nz) * sizeof(double);
+  hipLaunchKernelGGL(k_thomas, dim3(static_cast<unsigned>(blocks)), dim3(64), lds, st, v, a,
+                     static_cast<double*>(chk));
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 """GPU edge cases of the solve path against the CPU FP64 oracle: the longest axis the plans
-take (512 unknowns), the shortest ones (2 cells; a face-located axis with 2 unknowns), the
-largest batch (64 right-hand sides, each with its own shift), and the bounds that are refused.
+take (512 unknowns), the shortest ones (2 cells; a face-located axis with 2 unknowns), z lines
+of every length class for the two-ended Thomas solve, the largest batch (64 right-hand sides,
+each with its own shift), and the bounds that are refused.
 Tolerances as in test_gpu_parity.py: FP64 <= 1e-12, refined <= 1e-10.
 """
 import numpy as np
@@ -69,6 +70,21 @@ def test_shortest_axes(torch, precision, tol):
         f = workloads.rhs_uniform(41, 3, prob.shape_xyz)
         ref = _oracle(prob, f, [1.0] * 3)
         assert _err(_run(torch, prob, f, precision=precision), ref) <= tol, (n, precision)
+
+
+@pytest.mark.parametrize("nz,loc_z", [(2, fv.CELL), (3, fv.CELL), (3, fv.FACE), (33, fv.CELL), (34, fv.CELL),
+                                       (65, fv.CELL)])
+def test_tpt_z_lengths(torch, nz, loc_z):
+    # the z lines split at the middle row into a part eliminated from each end: two unknowns
+    # (one side empty), odd and even lengths, and lengths one past a 16-step segment
+    n = (7, 5, nz)
+    faces = tuple(workloads.stretched_faces(n[d], 1.5) for d in range(3))
+    prob = workloads.Problem(faces=faces, bc_lo=(D, N, D), bc_hi=(D, D, N), loc=(fv.CELL, fv.CELL, loc_z),
+                             sigma=0.5)
+    sig = [0.5, 1e-3, 40.0]
+    f = workloads.rhs_uniform(61 + nz, 3, prob.shape_xyz)
+    ref = _oracle(prob, f, sig)
+    assert _err(_run(torch, prob, f, sigma=sig, method="tpt"), ref) <= 1e-12
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3_ir", 1e-10)])
