@@ -58,11 +58,12 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
         flops = 2.0 * N[stage] * npts
         es = ELEM_BYTES[prec]
         # FP64 solve: reads f, writes u.  Low-precision refinement: the last product adds its
-        # correction into u.  Split-BF16: the first solve reads f (x_fwd_rhs) and writes u
-        # (z_inv_u) in FP64; later corrections are FP32, added by the separate update stage.
+        # correction into u.  Split-BF16 with refinement: the first solve reads f in FP64
+        # (x_fwd_rhs) and writes its result in FP32 (z_inv_u); corrections are FP32, added by the
+        # separate update stage.
         last = "none" if prec == "bf16x3" else "x_inv"
         s_in = 8 if ((stage == "x_fwd" and prec == "fp64") or stage == "x_fwd_rhs") else es
-        s_out = 8 if (stage == last or stage == "z_inv_u") else es
+        s_out = 8 if stage == last else es
         byts = (s_in + s_out) * npts
         if stage == last and prec != "fp64":
             byts = (es + 16) * npts          # read du (low), read + write u (FP64)
@@ -72,12 +73,15 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
                         avg_us=avg_s * 1e6, algorithmic_flops=flops, algorithmic_bytes=byts)
         return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", avg_us=avg_s * 1e6,
                     algorithmic_flops=flops, algorithmic_bytes=byts)
+    # split-BF16: the first refinement sweep reads the FP32 first solve (two sweeps in the
+    # workloads measured here); other paths read u in FP64
+    u_bytes = 4 if prec == "bf16x3" else 8
     if stage == "residual":
-        byts = (8 + 8 + ELEM_BYTES[prec]) * npts     # read u, f (FP64), write r (low)
+        byts = (u_bytes + 8 + ELEM_BYTES[prec]) * npts     # read u, f (FP64), write r (low)
     elif stage == "convert":
         byts = (8 + ELEM_BYTES[prec]) * npts
     elif stage == "update":
-        byts = (ELEM_BYTES[prec] + 16) * npts         # read du (FP32), read + write u (FP64)
+        byts = (ELEM_BYTES[prec] + u_bytes + 8) * npts    # read du (FP32), read u, write u (FP64)
     elif stage == "thomas":
         byts = 16 * npts                              # algorithmic: read g, write v once
     else:
@@ -375,9 +379,8 @@ TRAFFIC_STAGES = {
     ("bf16x3", "z_fwd_div"): ("void helm::k_rot_bf16x3<4, 4, 8, 1, true, float>", 8),
     ("bf16x3", "x_fwd"): ("void helm::k_rot_bf16x3<4, 4, 8, 0, true, float>", 8),
     ("bf16x3", "x_fwd_rhs"): ("void helm::k_rot_bf16x3<4, 4, 8, 0, true, double>", 12),
-    ("bf16x3", "z_inv_u"): ("void helm::k_rot_bf16x3<4, 4, 8, 3, true, float>", 12),
-    ("bf16x3", "residual"): ("void helm::k_stencil<float, 1>", 20),
-    ("bf16x3", "update"): ("helm::k_update", 20),
+    ("bf16x3", "residual"): ("void helm::k_stencil<float, 1, float>", 16),
+    ("bf16x3", "update"): ("void helm::k_update<2>", 16),
     ("fp64", "z_fwd_div"): ("void helm::k_left<double, 4, 4, 4, 1, 2, false>", 16),
     ("fp64", "y_fwd"): ("void helm::k_left<double, 4, 4, 4, 0, 2, false>", 16),
 }

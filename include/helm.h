@@ -190,7 +190,8 @@ enum {
   HELM_STAGE_X_INV, HELM_STAGE_THOMAS, HELM_STAGE_NULL_LINE, HELM_STAGE_RESIDUAL, HELM_STAGE_CONVERT,
   HELM_STAGE_APPLY, HELM_STAGE_OTHER, HELM_STAGE_UPDATE,
   /* split-BF16 first solve: the x-forward product reading the FP64 right-hand side, and the
-   * z-inverse product writing the FP64 solution */
+   * z-inverse product writing the solution (FP64, or FP32 into the workspace when refinement
+   * sweeps follow) */
   HELM_STAGE_X_FWD_RHS, HELM_STAGE_Z_INV_U, HELM_NSTAGES
 };
 helm_status helm_profile_enable(helm_plan* plan, int enable);

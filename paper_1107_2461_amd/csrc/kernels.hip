@@ -343,11 +343,14 @@ hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const d
 // XCD's L2.  Per point: 8 B of u, 8 B of f in, one value out, plus halo re-reads.
 constexpr int kStencilJS = 4;
 
-__device__ inline double lane_below(double v, int lane) { return __shfl(v, lane > 0 ? lane - 1 : 0); }
-__device__ inline double lane_above(double v, int lane) { return __shfl(v, lane < 63 ? lane + 1 : 63); }
+template <typename T>
+__device__ inline T lane_below(T v, int lane) { return __shfl(v, lane > 0 ? lane - 1 : 0); }
+template <typename T>
+__device__ inline T lane_above(T v, int lane) { return __shfl(v, lane < 63 ? lane + 1 : 63); }
 
-template <typename TOut, int MODE>  // MODE 0: out = H u, 1: out = f - H u
-__global__ __launch_bounds__(256) void k_stencil(const double* __restrict__ u,
+// TU: storage of u (FP64, or FP32 for the first solve's result, which is exact in FP64 once read)
+template <typename TOut, int MODE, typename TU>  // MODE 0: out = H u, 1: out = f - H u
+__global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
                                                  const double* __restrict__ f, TOut* __restrict__ out,
                                                  StencilArgs a, int zchunk, int nzc, int wx, int nbx, int nby) {
   constexpr int JS = kStencilJS;
@@ -385,11 +388,13 @@ __global__ __launch_bounds__(256) void k_stencil(const double* __restrict__ u,
     cyu[s] = (j0 + s + 1 < a.ny) ? a.cy[3 * j + 2] : 0.0;
     dxy[s] = a.sigma[r] + cxd + a.cy[3 * j + 1];
   }
-  const double* ucol = u + rbase + ic;
+  const TU* ucol = u + rbase + ic;
   auto at = [&](int k, int s) { return ucol + k * plane + static_cast<long long>(jr[s]) * a.nx; };
-  double um[JS], uc[JS + 2], up[JS + 2];
+  // u is held in its storage type and widened where it is used, so no conversion waits for a
+  // load ahead of the arithmetic
+  TU um[JS], uc[JS + 2], up[JS + 2];
 #pragma unroll
-  for (int s = 0; s < JS; ++s) um[s] = k0 > 0 ? *at(k0 - 1, s + 1) : 0.0;
+  for (int s = 0; s < JS; ++s) um[s] = k0 > 0 ? *at(k0 - 1, s + 1) : TU(0);
 #pragma unroll
   for (int s = 0; s < JS + 2; ++s) uc[s] = *at(k0, s);
   for (int k = k0; k < k1; ++k) {
@@ -397,21 +402,22 @@ __global__ __launch_bounds__(256) void k_stencil(const double* __restrict__ u,
     // x neighbours and f of plane k first, plane k+1 (next step's centre) last
 #pragma unroll
     for (int s = 0; s < JS; ++s) {
-      double lo = lane_below(uc[s + 1], lane), hi = lane_above(uc[s + 1], lane);
-      const double* p = at(k, s + 1);
+      TU lo = lane_below(uc[s + 1], lane), hi = lane_above(uc[s + 1], lane);
+      const TU* p = at(k, s + 1);
       if (lane == 0 && hx_lo) lo = p[-1];
       if (lane == 63 && hx_hi) hi = p[1];
-      xs[s] = (hx_lo ? cxl * lo : 0.0) + (hx_hi ? cxu * hi : 0.0);
+      xs[s] = (hx_lo ? cxl * static_cast<double>(lo) : 0.0) + (hx_hi ? cxu * static_cast<double>(hi) : 0.0);
       fv[s] = MODE == 1 ? f[rbase + k * plane + static_cast<long long>(jr[s + 1]) * a.nx + ic] : 0.0;
     }
     const bool has_up = k + 1 < a.nz;
 #pragma unroll
-    for (int s = 0; s < JS + 2; ++s) up[s] = has_up ? *at(k + 1, s) : 0.0;
+    for (int s = 0; s < JS + 2; ++s) up[s] = has_up ? *at(k + 1, s) : TU(0);
     const double czl = a.cz[3 * k], czd = a.cz[3 * k + 1], czu = a.cz[3 * k + 2];
 #pragma unroll
     for (int s = 0; s < JS; ++s) {
-      const double h = (dxy[s] + czd) * uc[s + 1] + czl * um[s] + czu * up[s + 1] + cyl[s] * uc[s] +
-                       cyu[s] * uc[s + 2] + xs[s];
+      const double h = (dxy[s] + czd) * static_cast<double>(uc[s + 1]) + czl * static_cast<double>(um[s]) +
+                       czu * static_cast<double>(up[s + 1]) + cyl[s] * static_cast<double>(uc[s]) +
+                       cyu[s] * static_cast<double>(uc[s + 2]) + xs[s];
       const double res = MODE == 1 ? fv[s] - h : h;
       if (iok && j0 + s < a.ny) out[rbase + k * plane + static_cast<long long>(j0 + s) * a.nx + i] = store_cvt<TOut>(res);
     }
@@ -428,8 +434,10 @@ __global__ __launch_bounds__(256) void k_convert(const double* __restrict__ f, T
   if (i < n) out[i] = store_cvt<TOut>(f[i]);
 }
 
-hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout, const StencilArgs& a,
-                   hipStream_t st) {
+namespace {
+template <typename TU>
+hipError_t stencil_any(int mode, const TU* u, const double* f, void* out, Prec tout, const StencilArgs& a,
+                       hipStream_t st) {
   const long long n = static_cast<long long>(a.nx) * a.ny * a.nz * a.nrhs;
   if (n == 0) return hipSuccess;
   if (mode == 2) {
@@ -457,8 +465,8 @@ hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec t
   const dim3 grid(static_cast<unsigned>(tiles)), block(256);
   auto launch = [&](auto out_type, auto mode_c) {
     using TOut = decltype(out_type);
-    hipLaunchKernelGGL((k_stencil<TOut, decltype(mode_c)::value>), grid, block, 0, st, u, f, static_cast<TOut*>(out),
-                       a, zchunk, nzc, wx, nbx, nby);
+    hipLaunchKernelGGL((k_stencil<TOut, decltype(mode_c)::value, TU>), grid, block, 0, st, u, f,
+                       static_cast<TOut*>(out), a, zchunk, nzc, wx, nbx, nby);
   };
   using M0 = std::integral_constant<int, 0>;
   using M1 = std::integral_constant<int, 1>;
@@ -470,27 +478,50 @@ hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec t
     mode == 1 ? launch(bf16_t{}, M1{}) : launch(bf16_t{}, M0{});
   return hipGetLastError();
 }
+}  // namespace
+
+hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout, const StencilArgs& a,
+                   hipStream_t st) {
+  return stencil_any(mode, u, f, out, tout, a, st);
+}
+
+hipError_t stencil_u32(int mode, const float* u, const double* f, void* out, Prec tout, const StencilArgs& a,
+                       hipStream_t st) {
+  if (mode != 0 && mode != 1) return hipErrorInvalidValue;
+  return stencil_any(mode, u, f, out, tout, a, st);
+}
 
 // ------------------------------------------------------------------ refinement update
 // Grid-stride over the points of one RHS (blockIdx.y); each lane updates 4 consecutive points
 // per step (16-byte FP32 load, two 16-byte FP64 load/stores).  Norms: wave max, then a block
-// max through LDS, then one striped atomic pair per workgroup.
-__global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const float* __restrict__ d, long long P,
-                                                int assign, unsigned long long* __restrict__ norms) {
+// max through LDS, then one striped atomic pair per workgroup.  SRC: the value d is added to:
+// 0 the FP64 u in place, 1 nothing (u = d), 2 an FP32 first solve u0 (u = u0 + d).
+template <int SRC>
+__global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const float* __restrict__ d,
+                                                const float* __restrict__ u0, long long P,
+                                                unsigned long long* __restrict__ norms) {
   typedef double d2v __attribute__((ext_vector_type(2)));
   __shared__ double sh[2][4];
   __shared__ int shbad[4];
   const int r = blockIdx.y;
   double* ur = u + r * P;
   const float* dr = d + r * P;
+  const float* u0r = SRC == 2 ? u0 + r * P : nullptr;
   double dm = 0.0, um = 0.0;
   bool bad = false;
   const long long stride = static_cast<long long>(gridDim.x) * 1024;
   for (long long i0 = (static_cast<long long>(blockIdx.x) * 256 + threadIdx.x) * 4; i0 < P; i0 += stride) {
     if (i0 + 3 < P && (P & 3) == 0) {
       const f4 dv = *reinterpret_cast<const f4*>(dr + i0);
-      d2v a = assign ? d2v{0, 0} : *reinterpret_cast<const d2v*>(ur + i0);
-      d2v b = assign ? d2v{0, 0} : *reinterpret_cast<const d2v*>(ur + i0 + 2);
+      d2v a = d2v{0, 0}, b = d2v{0, 0};
+      if constexpr (SRC == 0) {
+        a = *reinterpret_cast<const d2v*>(ur + i0);
+        b = *reinterpret_cast<const d2v*>(ur + i0 + 2);
+      } else if constexpr (SRC == 2) {
+        const f4 ov = *reinterpret_cast<const f4*>(u0r + i0);
+        a = d2v{static_cast<double>(ov[0]), static_cast<double>(ov[1])};
+        b = d2v{static_cast<double>(ov[2]), static_cast<double>(ov[3])};
+      }
       a[0] += dv[0];
       a[1] += dv[1];
       b[0] += dv[2];
@@ -506,7 +537,8 @@ __global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const fl
     } else {
       for (long long i = i0; i < i0 + 4 && i < P; ++i) {
         const double dv = dr[i];
-        const double un = (assign ? 0.0 : ur[i]) + dv;
+        const double old = SRC == 0 ? ur[i] : (SRC == 2 ? static_cast<double>(u0r[i]) : 0.0);
+        const double un = old + dv;
         ur[i] = un;
         bad = bad || !(dv == dv) || !(un == un);
         dm = fmax(dm, fabs(dv));
@@ -540,10 +572,16 @@ __global__ __launch_bounds__(256) void k_update(double* __restrict__ u, const fl
 }
 
 hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign, unsigned long long* norms,
-                    hipStream_t st) {
+                    hipStream_t st, const float* u0) {
   if (P <= 0 || nrhs <= 0) return hipSuccess;
   const long long blocks = std::min<long long>((P + 1023) / 1024, 2048);
-  hipLaunchKernelGGL(k_update, dim3(static_cast<unsigned>(blocks), nrhs), dim3(256), 0, st, u, d, P, assign, norms);
+  const dim3 grid(static_cast<unsigned>(blocks), nrhs), block(256);
+  if (u0)
+    hipLaunchKernelGGL(k_update<2>, grid, block, 0, st, u, d, u0, P, norms);
+  else if (assign)
+    hipLaunchKernelGGL(k_update<1>, grid, block, 0, st, u, d, u0, P, norms);
+  else
+    hipLaunchKernelGGL(k_update<0>, grid, block, 0, st, u, d, u0, P, norms);
   return hipGetLastError();
 }
 

@@ -98,11 +98,15 @@ struct StencilArgs {
 };
 hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout,
                    const StencilArgs& a, hipStream_t st);
+// Modes 0 and 1 with u stored in FP32 (each value is exact in FP64 once read).
+hipError_t stencil_u32(int mode, const float* u, const double* f, void* out, Prec tout, const StencilArgs& a,
+                       hipStream_t st);
 
-// Refinement update u += d (or u = d when assign != 0) for nrhs fields of P points, d FP32,
-// with per-RHS max|d| and max|u| (bit patterns, atomic max) into norms[2 r], norms[2 r + 1].
+// Refinement update u += d (u = d when assign != 0; u = u0 + d when u0, an FP32 first solve,
+// is given) for nrhs fields of P points, d FP32, with per-RHS max|d| and max|u| (bit patterns,
+// atomic max) into norms[2 r], norms[2 r + 1].
 hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign, unsigned long long* norms,
-                    hipStream_t st);
+                    hipStream_t st, const float* u0 = nullptr);
 // Zero `n` 64-bit words (a fill kernel, safe under stream capture).
 hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st);
 // Volume-weighted mean removal per RHS: x -= sum(vol * x) * inv_volsum   (FP64, in place,

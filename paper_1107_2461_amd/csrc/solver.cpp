@@ -393,9 +393,10 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
 
 // Workspace layout (each region 256-byte aligned):
 //   FP64:  W    nrhs*P doubles         (+ Thomas checkpoints for TPT_Z)
-//   low :  L1, L2  nrhs*P low-precision values each, norms 2*nrhs u64
+//   low :  L1, L2  nrhs*P low-precision values each (split-BF16 with refinement: also L3, the
+//          first solve in FP32), norms 2*nrhs u64
 static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t* off_a, size_t* off_b,
-                             size_t* off_norms, size_t* off_mean = nullptr) {
+                             size_t* off_norms, size_t* off_mean = nullptr, size_t* off_c = nullptr) {
   const size_t P = static_cast<size_t>(p->npts()) * nrhs;
   size_t t = 0;
   if (p->prec() == P_F64) {
@@ -410,6 +411,8 @@ static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t
     t = align_up(P * es, 256);
     *off_b = t;
     t += align_up(P * es, 256);
+    if (off_c) *off_c = t;
+    if (p->prec() == P_BF16X3 && p->refined()) t += align_up(P * 4, 256);
     *off_norms = t;
     t += align_up(2 * kMaxRhs * kNormStripes * sizeof(unsigned long long), 256);
   }
@@ -479,7 +482,7 @@ hipError_t timed(const helm_plan* p, int stage, hipStream_t st, F&& launch) {
 // `out` with epilogue epi_last (STORE in pr, or ACCUM into FP64 u).
 hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, void* b2, void* out, Epi epi_last,
                         int nrhs, const double* sig, unsigned long long* norms, int accum_zero, hipStream_t st,
-                        bool in_f64 = false) {
+                        bool in_f64 = false, bool u0_f32 = false, const float* u0 = nullptr) {
   const DevAxis& X = *p->ax[0];
   const DevAxis& Y = *p->ax[1];
   const DevAxis& Z = *p->ax[2];
@@ -522,9 +525,11 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
       return e;
     if (epi_last != EPI_ACCUM) return hipErrorInvalidValue;
     if (accum_zero) {
-      // first solve (u = 0): the product writes u in FP64 directly; its norms are not used
+      // first solve (u = 0): the product writes u directly, in FP64 as the result, or in FP32
+      // (u0_f32) when refinement follows: its error (~1e-7) is far above FP32 rounding, and the
+      // FP64 residual of the FP32 values is exact, so the next sweep corrects both
       return timed(p, HELM_STAGE_Z_INV_U, st, [&] {
-        return mode_rot(Z.sw3[1], nz, f1, false, out, nrhs, ny * nx, EPI_STORE_F64, ep, st);
+        return mode_rot(Z.sw3[1], nz, f1, false, out, nrhs, ny * nx, u0_f32 ? EPI_STORE : EPI_STORE_F64, ep, st);
       });
     }
     // a correction lands in FP32 (natural layout) and is added to u by a streaming kernel
@@ -533,8 +538,9 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
            return mode_rot(Z.sw3[1], nz, f1, false, f2, nrhs, ny * nx, EPI_STORE, ep, st);
          })) != hipSuccess)
       return e;
+    // u = u0 + du when the previous iterate is the FP32 first solve, else u += du
     return timed(p, HELM_STAGE_UPDATE, st, [&] {
-      return update_u(static_cast<double*>(out), f2, nx * ny * nz, nrhs, 0, norms, st);
+      return update_u(static_cast<double*>(out), f2, nx * ny * nz, nrhs, 0, norms, st, u0);
     });
   }
   const int ip = static_cast<int>(pr);
@@ -599,8 +605,8 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
                                   void* ws, void* stream, helm_info* info) {
   if (!p || !f || !u || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
   if (p->refined() && f == u) return HELM_EINVAL;
-  size_t total, off_a, off_b, off_n, off_m;
-  workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n, &off_m);
+  size_t total, off_a, off_b, off_n, off_m, off_c;
+  workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n, &off_m, &off_c);
   if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0) return HELM_EINVAL;
   double sig[kMaxRhs];
   for (int r = 0; r < nrhs; ++r) {
@@ -710,8 +716,14 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   const Prec store = pr == P_BF16X3 ? P_F32 : pr;  // storage type of the low-precision fields
   // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.
   if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
+  // Split-BF16 with refinement sweeps to follow keeps the first solve in FP32 (L3): the first
+  // residual and update then read 4 bytes of it per point instead of 8.
+  float* U0 = nullptr;
+  if (pr == P_BF16X3 && p->refined() && p->opts.max_sweeps > 1) U0 = reinterpret_cast<float*>(w + off_c);
   if (pr == P_BF16X3) {  // the first product reads f in FP64 directly
-    if (e == hipSuccess) e = tpf_products(p, pr, f, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 1, st, true);
+    if (e == hipSuccess)
+      e = tpf_products(p, pr, f, L2, L1, U0 ? static_cast<void*>(U0) : static_cast<void*>(u), EPI_ACCUM, nrhs, sig,
+                       norms, 1, st, true, U0 != nullptr);
   } else {
     if (e == hipSuccess)
       e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, store, sa, st); });
@@ -726,8 +738,12 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   bool conv = false;
   while (sweeps < p->opts.max_sweeps) {
     if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
-    if (e == hipSuccess) e = timed(p, HELM_STAGE_RESIDUAL, st, [&] { return stencil(1, u, f, L1, store, sa, st); });
-    if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st);
+    const float* u0 = sweeps == 1 ? U0 : nullptr;  // the iterate is still the FP32 first solve
+    if (e == hipSuccess)
+      e = timed(p, HELM_STAGE_RESIDUAL, st, [&] {
+        return u0 ? stencil_u32(1, u0, f, L1, store, sa, st) : stencil(1, u, f, L1, store, sa, st);
+      });
+    if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st, false, false, u0);
     if (e == hipSuccess)
       e = hipMemcpyAsync(hn.p, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st);
