@@ -354,6 +354,8 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
                                                  const double* __restrict__ f, TOut* __restrict__ out,
                                                  StencilArgs a, int zchunk, int nzc, int wx, int nbx, int nby) {
   constexpr int JS = kStencilJS;
+  if (a.zero && blockIdx.x == 0)
+    for (int q = threadIdx.x; q < a.nzero; q += blockDim.x) a.zero[q] = 0ull;
   // the wave index is uniform: the row segment (and its coefficients) then live in SGPRs
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nt = gridDim.x;
@@ -586,15 +588,6 @@ hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign
 }
 
 // ------------------------------------------------------------------ small helpers
-__global__ void k_zero_u64(unsigned long long* p, long long n) {
-  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ull;
-}
-hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u64, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, p, n);
-  return hipGetLastError();
-}
 
 // Deterministic volume-weighted sums: stage 1 writes one partial per block, stage 2 sums
 // them in a fixed order, stage 3 subtracts the mean.

@@ -95,6 +95,10 @@ struct StencilArgs {
   const double* cz;   // [3 * nz]
   int nx, ny, nz, nrhs;
   double sigma[kMaxRhs];
+  // optional: the first workgroup clears these words (the refinement norms of the sweep the
+  // residual starts), so no launch of its own is needed
+  unsigned long long* zero = nullptr;
+  int nzero = 0;
 };
 hipError_t stencil(int mode, const double* u, const double* f, void* out, Prec tout,
                    const StencilArgs& a, hipStream_t st);
@@ -107,8 +111,6 @@ hipError_t stencil_u32(int mode, const float* u, const double* f, void* out, Pre
 // atomic max) into norms[2 r], norms[2 r + 1].
 hipError_t update_u(double* u, const float* d, long long P, int nrhs, int assign, unsigned long long* norms,
                     hipStream_t st, const float* u0 = nullptr);
-// Zero `n` 64-bit words (a fill kernel, safe under stream capture).
-hipError_t zero_u64(unsigned long long* p, long long n, hipStream_t st);
 // Volume-weighted mean removal per RHS: x -= sum(vol * x) * inv_volsum   (FP64, in place,
 // deterministic order).  scratch: nrhs * (kMeanBlocks + 1) doubles of device memory.
 constexpr int kMeanBlocks = 1024;

@@ -714,8 +714,8 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   unsigned long long* norms = reinterpret_cast<unsigned long long*>(w + off_n);
   const StencilArgs sa = stencil_args(p, nrhs, sig);
   const Prec store = pr == P_BF16X3 ? P_F32 : pr;  // storage type of the low-precision fields
-  // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.
-  if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
+  // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.  Its norms are not read: the
+  // first correction is measured against u itself.
   // Split-BF16 with refinement sweeps to follow keeps the first solve in FP32 (L3): the first
   // residual and update then read 4 bytes of it per point instead of 8.
   float* U0 = nullptr;
@@ -737,11 +737,13 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   double last = 0.0, prev = 1.0;  // the first solve's "correction" is u itself
   bool conv = false;
   while (sweeps < p->opts.max_sweeps) {
-    if (e == hipSuccess) e = timed(p, HELM_STAGE_OTHER, st, [&] { return zero_u64(norms, 2 * nrhs * kNormStripes, st); });
     const float* u0 = sweeps == 1 ? U0 : nullptr;  // the iterate is still the FP32 first solve
+    StencilArgs sz = sa;  // the residual also clears this sweep's norm stripes
+    sz.zero = norms;
+    sz.nzero = 2 * nrhs * kNormStripes;
     if (e == hipSuccess)
       e = timed(p, HELM_STAGE_RESIDUAL, st, [&] {
-        return u0 ? stencil_u32(1, u0, f, L1, store, sa, st) : stencil(1, u, f, L1, store, sa, st);
+        return u0 ? stencil_u32(1, u0, f, L1, store, sz, st) : stencil(1, u, f, L1, store, sz, st);
       });
     if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st, false, false, u0);
     if (e == hipSuccess)
