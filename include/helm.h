@@ -212,7 +212,12 @@ helm_status helm_profile_stages(helm_plan* plan, unsigned stage_mask);
  * `max_bypass_ms`).  Each slot owns a HIP stream and a host worker thread, so admitted
  * solves run concurrently on the device and new requests are admitted while others are in
  * flight.  Plans (1D eigenbases) are cached on the device by their axis definition and
- * reused across requests.  Times are seconds since server creation (steady clock).
+ * reused across requests.  When a request is admitted, queued requests on the same plan ride
+ * along (up to 64 right-hand sides in all, within the budget, passing earlier requests only
+ * under the same bypass rule): they are solved as one multi-RHS solve with each request's
+ * shifts, their f and u staged through the workspace (2 x 8 bytes per point and right-hand
+ * side more), and their records carry the batch size.  Times are seconds since server
+ * creation (steady clock).
  * --------------------------------------------------------------------------------------- */
 typedef struct helm_server helm_server;
 
@@ -224,8 +229,10 @@ typedef struct {
   double t_submit;         /* submit time */
   double t_admit;          /* admission time */
   double t_done;           /* completion time (device work finished) */
-  size_t footprint;        /* device workspace bytes charged against the budget */
+  size_t footprint;        /* device workspace bytes charged against the budget (for the whole
+                              solve when requests were solved together) */
   int slot;                /* slot that ran it */
+  int batch;               /* requests solved together in its multi-RHS solve (1 = alone) */
 } helm_request_record;
 
 /* Creates a server with `slots` concurrent solve slots (1..16) and a device-workspace budget

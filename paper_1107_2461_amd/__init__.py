@@ -313,7 +313,7 @@ class Server:
             self._live.pop(r.id, None)
             out.append(dict(id=r.id, status=r.status, sweeps=r.sweeps, last_correction=r.last_correction,
                             t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done, footprint=r.footprint,
-                            slot=r.slot))
+                            slot=r.slot, batch=r.batch))
         return out
 
     def drain(self):

@@ -42,7 +42,7 @@ class HelmInfo(C.Structure):
 class HelmRequestRecord(C.Structure):
     _fields_ = [("id", C.c_longlong), ("status", C.c_int), ("sweeps", C.c_int), ("last_correction", C.c_double),
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint", C.c_size_t),
-                ("slot", C.c_int)]
+                ("slot", C.c_int), ("batch", C.c_int)]
 
 
 class HelmServerStats(C.Structure):

@@ -5,7 +5,9 @@
 // depend on the time step (Section 1).  The server keeps the eigenbases resident, admits
 // queued requests by free slot and device-workspace budget, and runs each admitted request on
 // its slot's stream from the slot's worker thread, so requests overlap on the GPU and new
-// ones are admitted while others are in flight.
+// ones are admitted while others are in flight.  Queued requests on the plan of a request being
+// admitted ride along with it: one multi-RHS solve with every request's shifts (the velocity
+// components of a time step share their grids), their f and u staged contiguously.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -62,11 +64,23 @@ struct Request {
   PlanRef plan;
   std::vector<double> sigma;
   int nrhs = 0;
+  long long npts = 0;  // unknowns per right-hand side
   const double* f = nullptr;
   double* u = nullptr;
   double t_submit = 0.0, t_admit = 0.0;
-  size_t foot = 0;
+  size_t foot = 0;  // bytes charged: the solve's workspace (+ staging when others ride along)
+  std::vector<std::unique_ptr<Request>> riders;  // same-plan requests solved with this one
 };
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Footprint of one multi-RHS solve of `total` right-hand sides on plan p with staging for f and
+// u, or 0 when the size cannot be had.
+inline size_t batch_foot(helm_plan* p, int total, long long npts) {
+  size_t ws = 0;
+  if (helm_workspace_size(p, total, &ws) != HELM_OK) return 0;
+  return align256(ws) + 2 * static_cast<size_t>(total) * static_cast<size_t>(npts) * sizeof(double);
+}
 
 struct Slot {
   std::thread worker;
@@ -125,6 +139,7 @@ struct helm_server {
       std::unique_ptr<Request> r = std::move(queue[i]);
       queue.erase(queue.begin() + i);
       r->t_admit = now();
+      add_riders(r.get());
       used += r->foot;
       for (auto& s : slots)
         if (!s->job) {
@@ -133,6 +148,81 @@ struct helm_server {
           break;
         }
     }
+  }
+
+  // Pull queued requests on r's plan into r's solve while the right-hand sides fit one solve
+  // (64) and the grown footprint fits the budget.  Riders pass requests queued before them only
+  // while the head of the queue has waited less than max_bypass (or is itself the rider).
+  void add_riders(Request* r) {
+    int total = r->nrhs;
+    const double t = now();
+    for (size_t j = 0; j < queue.size();) {
+      Request& q = *queue[j];
+      const bool head_ok = j == 0 || t - queue.front()->t_submit < max_bypass;
+      if (q.plan != r->plan || total + q.nrhs > 64 || !head_ok) {
+        ++j;
+        continue;
+      }
+      const size_t grown = batch_foot(r->plan.get(), total + q.nrhs, r->npts);
+      if (grown == 0 || used + grown > budget) break;
+      r->foot = grown;
+      total += q.nrhs;
+      queue[j]->t_admit = t;
+      r->riders.push_back(std::move(queue[j]));
+      queue.erase(queue.begin() + j);
+    }
+  }
+
+  // One request alone, or a batch as one multi-RHS solve through staging buffers after the
+  // solve's workspace; a batch the solver refuses (e.g. mixed singular and regular shifts on an
+  // all-Neumann plan) is solved request by request.  Returns a status per request.
+  std::vector<helm_status> run(Request& r, Slot& s, helm_info& info) {
+    std::vector<Request*> reqs{&r};
+    for (auto& q : r.riders) reqs.push_back(q.get());
+    std::vector<helm_status> out(reqs.size(), HELM_OK);
+    auto one = [&](Request& q) -> helm_status {
+      helm_status st = helm_solve(q.plan.get(), q.f, q.u, q.nrhs, q.sigma.data(), s.ws, s.stream, &info);
+      if (st == HELM_OK && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
+      return st;
+    };
+    if (reqs.size() == 1) {
+      out[0] = one(r);
+      return out;
+    }
+    int total = 0;
+    std::vector<double> sig;
+    for (Request* q : reqs) {
+      total += q->nrhs;
+      sig.insert(sig.end(), q->sigma.begin(), q->sigma.end());
+    }
+    size_t ws = 0;
+    helm_status st = helm_workspace_size(r.plan.get(), total, &ws);
+    double* F = reinterpret_cast<double*>(static_cast<char*>(s.ws) + align256(ws));
+    double* U = F + static_cast<size_t>(total) * r.npts;
+    const size_t per = static_cast<size_t>(r.npts) * sizeof(double);
+    size_t o = 0;
+    for (Request* q : reqs) {
+      if (st == HELM_OK && hipMemcpyAsync(F + o * r.npts, q->f, q->nrhs * per, hipMemcpyDeviceToDevice, s.stream) !=
+                               hipSuccess)
+        st = HELM_EDEVICE;
+      o += q->nrhs;
+    }
+    if (st == HELM_OK) st = helm_solve(r.plan.get(), F, U, total, sig.data(), s.ws, s.stream, &info);
+    if (st == HELM_EINVAL) {
+      for (size_t i = 0; i < reqs.size(); ++i) out[i] = one(*reqs[i]);
+      return out;
+    }
+    if (st == HELM_OK || st == HELM_ENOTCONVERGED) {
+      o = 0;
+      for (Request* q : reqs) {
+        if (hipMemcpyAsync(q->u, U + o * r.npts, q->nrhs * per, hipMemcpyDeviceToDevice, s.stream) != hipSuccess)
+          st = HELM_EDEVICE;
+        o += q->nrhs;
+      }
+    }
+    if ((st == HELM_OK || st == HELM_ENOTCONVERGED) && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
+    std::fill(out.begin(), out.end(), st);
+    return out;
   }
 
   void work(int k) {
@@ -158,24 +248,31 @@ struct helm_server {
         else
           st = HELM_ENOMEM;
       }
-      if (st == HELM_OK) st = helm_solve(r.plan.get(), r.f, r.u, r.nrhs, r.sigma.data(), s.ws, s.stream, &info);
-      if (st == HELM_OK && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
-      helm_request_record rec{};
-      rec.id = r.id;
-      rec.status = st;
-      rec.sweeps = info.sweeps;
-      rec.last_correction = info.last_correction;
-      rec.t_submit = r.t_submit;
-      rec.t_admit = r.t_admit;
-      rec.t_done = now();
-      rec.footprint = r.foot;
-      rec.slot = k;
+      std::vector<helm_status> sts(1 + r.riders.size(), st);
+      if (st == HELM_OK) sts = run(r, s, info);
+      const double t_done = now();
+      std::vector<helm_request_record> recs;
+      for (size_t i = 0; i < sts.size(); ++i) {
+        const Request& q = i == 0 ? r : *r.riders[i - 1];
+        helm_request_record rec{};
+        rec.id = q.id;
+        rec.status = sts[i];
+        rec.sweeps = info.sweeps;
+        rec.last_correction = info.last_correction;
+        rec.t_submit = q.t_submit;
+        rec.t_admit = q.t_admit;
+        rec.t_done = t_done;
+        rec.footprint = r.foot;
+        rec.slot = k;
+        rec.batch = static_cast<int>(sts.size());
+        recs.push_back(rec);
+      }
       {
         std::lock_guard<std::mutex> lk(mu);
         used -= r.foot;
         s.job.reset();
-        done.push_back(rec);
-        ++completed;
+        for (auto& rec : recs) done.push_back(rec);
+        completed += static_cast<long long>(recs.size());
         admit_locked();
       }
       cv_done.notify_all();
@@ -255,6 +352,8 @@ extern "C" helm_status helm_server_submit(helm_server* s, const helm_grid* grid,
   r->plan = plan;
   r->sigma.assign(sigma, sigma + nrhs);
   r->nrhs = nrhs;
+  r->npts = 1;
+  for (int d = 0; d < 3; ++d) r->npts *= grid->loc[d] == HELM_FACE ? grid->n[d] - 1 : grid->n[d];
   r->f = f;
   r->u = u;
   r->t_submit = t_submit;

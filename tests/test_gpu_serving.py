@@ -84,8 +84,9 @@ def test_mix_equals_alone_and_overlaps(torch, precision):
     print(f"{precision}: {bitwise}/{len(reqs)} results bitwise identical alone and in the mix")
     # budget and slots respected at every admission instant; some requests ran concurrently
     for t in sorted({x["t_admit"] for x in recs}):
-        live = [x for x in recs if x["t_admit"] <= t < x["t_done"]]
-        assert sum(x["footprint"] for x in live) <= budget
+        # requests solved together share one solve (slot, completion time) and its footprint
+        live = {(x["slot"], x["t_done"]): x["footprint"] for x in recs if x["t_admit"] <= t < x["t_done"]}
+        assert sum(live.values()) <= budget
         assert len(live) <= 4
     overl = sum(1 for a in recs for b in recs
                 if a["id"] < b["id"] and a["t_admit"] < b["t_done"] and b["t_admit"] < a["t_done"])
@@ -98,6 +99,40 @@ def test_mix_equals_alone_and_overlaps(torch, precision):
     outs_s, _ = _run_server(torch, small, precision, budget=64 << 20, slots=4, warm=False)
     for r, prob, f in small:
         assert _same(torch, _alone(torch, prob, f, precision), outs_s[r["rid"]]), r
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3_ir", 1e-10)])
+def test_same_plan_requests_ride_along(torch, precision, tol):
+    # one slot: while the first request of a plan runs, the next ones queue and are then solved
+    # together as one multi-RHS solve, each with its own shifts; every result must equal the
+    # request solved alone, and the budget counts the batch (with its staging) once
+    from paper_1107_2461_amd import Server
+    n = (48, 40, 36)
+    faces = tuple(workloads.stretched_faces(n[d], 1.5) for d in range(3))
+    prob = workloads.Problem(faces=faces, bc_lo=(1, 0, 0), bc_hi=(0, 0, 1), sigma=1.0)
+    shapes = [(1, [0.5]), (3, [10.0, 0.01, 3.0]), (2, [1.0, 200.0]), (1, [0.2]), (2, [7.0, 7.0])]
+    fs = [torch.from_numpy(workloads.rhs_uniform(80 + i, k, prob.shape_xyz)).to("cuda")
+          for i, (k, _) in enumerate(shapes)]
+    budget = 1 << 30
+    srv = Server(budget, slots=1, precision=precision, max_bypass_ms=1000.0)
+    for rnd in range(2):   # the first round builds the plan; the second runs with it resident
+        us = [torch.empty_like(f) for f in fs]
+        for i, ((k, sig), f) in enumerate(zip(shapes, fs)):
+            srv.submit(10 * rnd + i, prob.faces, f, us[i], sig, prob.bc_lo, prob.bc_hi)
+        srv.drain()
+        recs = srv.poll(max_records=64)
+    srv.close()
+    torch.cuda.synchronize()
+    assert len(recs) == len(shapes) and all(r["status"] == 0 for r in recs), recs
+    assert max(r["batch"] for r in recs) >= 2, recs
+    solves = {(r["slot"], r["t_done"]): r["footprint"] for r in recs}
+    assert all(fp <= budget for fp in solves.values())
+    from paper_1107_2461_amd import Plan
+    for i, ((k, sig), f) in enumerate(zip(shapes, fs)):
+        plan = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, precision=precision)
+        ua = plan.solve(f, sigma=sig)
+        torch.cuda.synchronize()
+        assert float((ua - us[i]).norm() / ua.norm()) <= tol, (i, precision)
 
 
 def test_tight_budget_serialises(torch):
