@@ -126,15 +126,15 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     # 2) the timed run: only the dominant stage's launches are bracketed (on the solve's stream)
     plan.profile(True, stages=[dom])
     plan.profile_read()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     sweeps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record()
+    ev0.record()
     for i in range(steps):
         plan.solve(f_dev, out=u, workspace=ws)
-        ev[i + 1].record()
         sweeps.append(plan.last_info["sweeps"])
+    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     timed = plan.profile_read()
@@ -142,8 +142,17 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     dms, dn = timed[dom]
     dom_rl = stage_roofline(dom, dms, dn, N, npts, lowp)
     dom_rl["frac"] = dom_rl["achieved"] / dom_rl["peak"]
+    total_ms = ev0.elapsed_time(ev1)
+    # 3) per-solve latency: the same solves, each between two events (torch's events fence the
+    # caches at every record, so they stay out of the timed run)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(steps):
+        plan.solve(f_dev, out=u, workspace=ws)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
     lat_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
-    total_ms = ev[0].elapsed_time(ev[steps])
     res = dict(ms_per_step=total_ms / steps, wall_ms_per_step=wall * 1e3 / steps,
                pts_per_s=npts / (total_ms / steps / 1e3), p50_ms=float(np.percentile(lat_ms, 50)),
                p99_ms=float(np.percentile(lat_ms, 99)), sweeps=int(np.median(sweeps)))
@@ -414,6 +423,8 @@ PROFILE_COMMANDS = (
     "python -u bench.py --steps 2 --warmup 0 --no-cpu-baseline --paths bf16x3_ir,fp64 --copy-ref-mb 1024",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/write -o w -- "
     "python -u bench.py --steps 2 --warmup 0 --no-cpu-baseline --paths bf16x3_ir,fp64 --copy-ref-mb 1024",
+    "rocprofv3 --pmc MfmaUtil MfmaFlopsBF16 MfmaFlopsF64 --output-format csv -d {d}/mfma -o m -- "
+    "python -u bench.py --steps 2 --warmup 0 --no-cpu-baseline --paths bf16x3_ir,fp64",
 )
 # (path family, stage) -> (kernel name prefix in the trace, algorithmic bytes per point)
 TRAFFIC_STAGES = {
@@ -499,6 +510,30 @@ def summarize_profiles(d, copy_mb=1024, npts=256 ** 3, workload="256^3 Helmholtz
              "kernel sources they were measured on (bench.py reports null once those sources change)."]
     with open(os.path.join(prof_dir, "hbm_traffic_helmholtz_256cube.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    # matrix-core use of the mode products: busy share of the SIMDs' MFMA units and MFMA flops
+    mrows = _read_csv(os.path.join(d, "mfma", "**", "*counter_collection.csv"))
+    if mrows:
+        acc = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in mrows:
+            acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        alg = 2.0 * 256 * npts   # one 256-point contraction of every grid point
+        lines = [f"# Matrix-core use per launch, {workload}", "", "Counter run (repo root, one MI355X):", "",
+                 "```", cmds[3], "```", "",
+                 "MfmaUtil: MFMA busy cycles over active cycles and SIMDs (%).  MFMA flops: as counted by the",
+                 "hardware (512 per MOPS unit); a split-BF16 product issues six bfloat16 products per term.",
+                 "", "| kernel | launches | MfmaUtil % | MFMA TFLOP per launch | / algorithmic |",
+                 "|---|---:|---:|---:|---:|"]
+        rows = []
+        for k, cs in acc.items():
+            fl = sum(sum(cs.get(c, [0.0])) / max(1, len(cs.get(c, [0.0]))) for c in ("MfmaFlopsBF16", "MfmaFlopsF64"))
+            if fl <= 0:
+                continue
+            util = sum(cs["MfmaUtil"]) / len(cs["MfmaUtil"]) if cs.get("MfmaUtil") else float("nan")
+            rows.append((fl, f"| `{k.split('(')[0][:110]}` | {len(cs.get('MfmaUtil', []))} | {util:.1f} | "
+                             f"{fl / 1e12:.4f} | {fl / alg:.2f} |"))
+        lines += [r for _, r in sorted(rows, key=lambda t: -t[0])]
+        with open(os.path.join(prof_dir, "mfma_util_helmholtz_256cube.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
     log(f"[bench] profiles written from {d}")
 
 

@@ -246,7 +246,8 @@ struct StageProfiler {
   hipEvent_t take() {
     if (used == pool.size()) {
       hipEvent_t e = nullptr;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      // timing only: no system-scope fence (a cache writeback and invalidate) at each record
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       pool.push_back(e);
     }
     return pool[used++];
