@@ -426,6 +426,10 @@ PROFILE_COMMANDS = (
     "rocprofv3 --pmc MfmaUtil MfmaFlopsBF16 MfmaFlopsF64 --output-format csv -d {d}/mfma -o m -- "
     "python -u bench.py --steps 2 --warmup 0 --no-cpu-baseline --paths bf16x3_ir,fp64",
 )
+# A kernel trace of the 3-RHS 128^3 workload (FP64 TPF, TPT with the Thomas kernel, split-BF16).
+PROFILE_TRACE_128 = ("rocprofv3 --kernel-trace --stats --output-format csv -d {d}/kt128 -o kt -- "
+                     "python -u bench.py --workload multirhs_128 --steps 5 --warmup 1 --no-cpu-baseline "
+                     "--paths fp64,tpt,bf16x3_ir")
 # (path family, stage) -> (kernel name prefix in the trace, algorithmic bytes per point)
 TRAFFIC_STAGES = {
     ("bf16x3", "z_fwd_div"): ("void helm::k_rot_bf16x3<4, 4, 8, 1, true, float>", 8),
@@ -455,17 +459,24 @@ def summarize_profiles(d, copy_mb=1024, npts=256 ** 3, workload="256^3 Helmholtz
     os.makedirs(prof_dir, exist_ok=True)
     cmds = [c.format(d=d) for c in PROFILE_COMMANDS]
     # kernel durations
-    stats = _read_csv(os.path.join(d, "kt", "**", "*kernel_stats.csv"))
-    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    lines = [f"# Kernel durations, {workload}, all arithmetic paths", "", "Command (repo root, one MI355X):", "",
-             "```", cmds[0], "```", "", "Top 24 kernels by total time (`*_kernel_stats.csv`).", "",
-             "| calls | avg (us) | total (ms) | kernel |", "|---:|---:|---:|---|"]
-    for r in stats[:24]:
-        name = r["Name"] if len(r["Name"]) < 150 else r["Name"][:147] + "..."
-        lines.append(f"| {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
-                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | `{name}` |")
-    with open(os.path.join(prof_dir, "kernel_stats_helmholtz_256cube.md"), "w") as fh:
-        fh.write("\n".join(lines) + "\n")
+    def kernel_table(sub, title, cmd, out_name):
+        stats = _read_csv(os.path.join(d, sub, "**", "*kernel_stats.csv"))
+        if not stats:
+            return
+        stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        lines = [f"# Kernel durations, {title}", "", "Command (repo root, one MI355X):", "",
+                 "```", cmd, "```", "", "Top 24 kernels by total time (`*_kernel_stats.csv`).", "",
+                 "| calls | avg (us) | total (ms) | kernel |", "|---:|---:|---:|---|"]
+        for r in stats[:24]:
+            name = r["Name"] if len(r["Name"]) < 150 else r["Name"][:147] + "..."
+            lines.append(f"| {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.2f} | `{name}` |")
+        with open(os.path.join(prof_dir, out_name), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+
+    kernel_table("kt", f"{workload}, all arithmetic paths", cmds[0], "kernel_stats_helmholtz_256cube.md")
+    kernel_table("kt128", "128^3 x 3 RHS (tau = 1e-3, 1, 1e2): FP64 TPF, TPT (Thomas in z), split-BF16",
+                 PROFILE_TRACE_128.format(d=d), "kernel_stats_helmholtz_128cube_x3.md")
     # HBM traffic: per-dispatch counters, calibrated on the copy of copy_mb MiB
     per = {}
     scale = {}
