@@ -414,8 +414,8 @@ def run_serving(torch, args):
 
 # ---------------------------------------------------------------------------------------
 # Profile summaries (profiles/*.md, profiles/traffic.json) from rocprofv3 CSV output.
-# Usage, after the three rocprofv3 runs listed in PROFILE_COMMANDS (run from the repo root):
-#   python bench.py --summarize-profiles gpurun_out/prof
+# Usage, after the rocprofv3 runs listed in PROFILE_COMMANDS and PROFILE_TRACE_128 (repo root):
+#   python bench.py --summarize-profiles <dir>   (the -d directory given to those runs)
 PROFILE_COMMANDS = (
     "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/kt -o kt -- "
     "python -u bench.py --steps 5 --warmup 1 --no-cpu-baseline",
