@@ -63,6 +63,12 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   constexpr int CHUNKS = RB * 64;         // 8-element chunks per k-block tile
   constexpr int CPT = (CHUNKS + 255) / 256;
   __shared__ u16x8 lds[2][3][RB * 64];    // [buffer][piece][row block * 64 + lane]
+  // divide: lambda_x + lambda_y + sigma of every tile row and lambda_z of every output column,
+  // rounded to FP32 and staged before the main loop, so the epilogue waits on no global load
+  constexpr int NSH = EPI == EPI_DIVIDE ? MT : 4;
+  constexpr int NLZ = EPI == EPI_DIVIDE ? W * NB * 16 : 4;
+  __shared__ __align__(16) float sh_shift[NSH];
+  __shared__ float sh_lamz[NLZ];
 
   const int tid = threadIdx.x;
   // the wave index is uniform: keep it (and every B-fragment base address) in scalar registers
@@ -146,6 +152,22 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   raw_t stage[DEPTH][CPT];
   u16x8 bcur[NB][3];
   load_tile(0, stage[0]);
+  if constexpr (EPI == EPI_DIVIDE) {
+    // the parts of the denominator are summed in FP64 and each sum rounded once to FP32; an
+    // exact FP64 cancellation lamz + shift = 0 stays exact (the two roundings are negatives of
+    // each other), so the FP32 zero test sees the null mode
+    const long long r0 = mwg / PQ;
+    for (int i = tid; i < MT; i += 256) {
+      const long long row = mwg + i;
+      float sv = 1.f;  // rows past the end: never stored
+      if (row < Mrows) {
+        const long long rr = rhs_of_row(row, r0, PQ);
+        sv = static_cast<float>(ep.lamxy[row - rr * PQ] + ep.sigma[rr]);
+      }
+      sh_shift[i] = sv;
+    }
+    for (int a = tid; a < NLZ; a += 256) sh_lamz[a] = a < K ? static_cast<float>(ep.lamz[a]) : 1.f;
+  }
   store_tile(0, stage[0]);
 #pragma unroll
   for (int d = 0; d < DEPTH; ++d)
@@ -185,54 +207,17 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
 
   // epilogue: lane holds rows m = mwg + (rb0 + mb)*16 + 4g + t (t < 4), column a = (cb0 + nb)*16 + l16
   const long long r_lo = mwg / PQ;
-  // Divide: every eigenvalue load is issued before the first store.  The vector-memory
-  // counter also counts stores, so a load issued after a store would wait for the store.
-  // The parts of the denominator are summed in FP64 and rounded once to FP32, the precision
-  // of the data.  An exact FP64 cancellation lamz + shift = 0 stays exact after rounding
-  // (the two roundings are negatives of each other), so the FP32 zero test sees the null mode.
   [[maybe_unused]] float shift[EPI == EPI_DIVIDE ? MB : 1][4];
   [[maybe_unused]] float lamz_c[EPI == EPI_DIVIDE ? NB : 1];
   if constexpr (EPI == EPI_DIVIDE) {
-    if (PQ >= MT) {
-      // a tile meets at most one RHS boundary: branch-free row split, so the 4 * MB loads issue
-      // back to back (rows past the end read the last row; their results are not stored)
-      const double sg0 = ep.sigma[r_lo];
-      const double sg1 = r_lo + 1 < R ? ep.sigma[r_lo + 1] : 0.0;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;
-        if constexpr (VEC) {
-          // the lane's four rows are four consecutive, aligned pq of one RHS: one 32-byte load
-          const long long o = (mq < Mrows ? mq : 0) - (mq < Mrows ? r_lo * PQ : 0);
-          const bool nxt = o >= PQ;
-          const d4v l4 = *reinterpret_cast<const d4v*>(ep.lamxy + (nxt ? o - PQ : o));
+    for (int mb = 0; mb < MB; ++mb) {
+      const f4 s4 = *reinterpret_cast<const f4*>(&sh_shift[(rb0 + mb) * 16 + 4 * g]);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) shift[mb][t] = static_cast<float>(l4[t] + (nxt ? sg1 : sg0));
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const long long o = min(mq + t, Mrows - 1) - r_lo * PQ;
-            const bool nxt = o >= PQ;
-            shift[mb][t] = static_cast<float>(ep.lamxy[nxt ? o - PQ : o] + (nxt ? sg1 : sg0));
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const long long r = rhs_of_row(mq + t, r_lo, PQ);
-          shift[mb][t] = (mq + t < Mrows) ? static_cast<float>(ep.lamxy[mq + t - r * PQ] + ep.sigma[r]) : 1.f;
-        }
-      }
+      for (int t = 0; t < 4; ++t) shift[mb][t] = s4[t];
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int a = (cb0 + nb) * 16 + l16;
-      lamz_c[nb] = a < K ? static_cast<float>(ep.lamz[a]) : 1.f;
-    }
+    for (int nb = 0; nb < NB; ++nb) lamz_c[nb] = sh_lamz[(cb0 + nb) * 16 + l16];
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
@@ -274,17 +259,11 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
         float* Y = static_cast<float*>(Yv);
         f4 v = acc[mb][nb];
         if constexpr (EPI == EPI_DIVIDE) {
-          // FP32 divide: rcp estimate + one Newton step
+          // FP32 divide by the hardware reciprocal (1 ulp, at the precision of the data)
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const float d = lamz_c[nb] + shift[mb][t];
-            if (d == 0.f) {
-              v[t] = ep.eq28 ? v[t] : 0.f;
-            } else {
-              float r = __builtin_amdgcn_rcpf(d);
-              r = fmaf(r, fmaf(-d, r, 1.f), r);
-              v[t] *= r;
-            }
+            v[t] = d == 0.f ? (ep.eq28 ? v[t] : 0.f) : v[t] * __builtin_amdgcn_rcpf(d);
           }
         }
         if (full) {
