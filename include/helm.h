@@ -81,7 +81,8 @@ typedef struct {
   double ir_tol;            /* refinement stops when the correction max|du| / max|u| of a sweep, or
                                its product with the observed contraction factor (the predicted
                                next correction, when that factor is below 1/2), is <= ir_tol
-                               (default 1e-11) */
+                               (default 1e-11).  0: exactly max_sweeps solves with no norm read
+                               back, for callers that know their sweep count (see helm_solve) */
   int max_sweeps;           /* refinement sweep limit, including the first solve (default 12) */
   int null_mode;            /* HELM_NULL_PROJECT (default) or HELM_NULL_PAPER_EQ28 */
 } helm_opts;
@@ -89,7 +90,8 @@ typedef struct {
 typedef struct {
   int sweeps;               /* low-precision solves performed (1 for the plain precisions) */
   double last_correction;   /* max|du| / max|u| of the last refinement sweep (0 if none) */
-  int converged;            /* 1 if the refinement tolerance was met (always 1 without IR) */
+  int converged;            /* 1 if the refinement tolerance was met (always 1 without IR), 0 if
+                               not, -1 if not checked (ir_tol = 0; last_correction is then -1) */
   int iterations;           /* GMRES iterations (pressure-matrix solve only) */
   double residual;          /* final relative residual (pressure-matrix solve only) */
 } helm_info;
@@ -122,7 +124,9 @@ helm_status helm_workspace_size(const helm_plan* plan, int nrhs, size_t* bytes);
  * workspace of at least helm_workspace_size bytes (256-byte aligned).  Without
  * refinement the call is fully asynchronous on `stream`.  With refinement each sweep
  * ends with one 16-byte device-to-host copy of the correction norms, so the call
- * returns after the device work is done.  info (host, nullable) receives the sweep
+ * returns after the device work is done; with ir_tol = 0 it runs exactly max_sweeps
+ * sweeps and reads nothing back, so it is asynchronous too (and launches only kernels,
+ * which a caller may capture into a graph).  info (host, nullable) receives the sweep
  * count and final correction.  Errors: EINVAL, ESINGULAR, ENOTCONVERGED (u holds the
  * last iterate), ENONFINITE, EDEVICE. */
 helm_status helm_solve(helm_plan* plan, const double* f, double* u, int nrhs,

@@ -139,8 +139,9 @@ class Plan:
         else:
             st = fn(self._h, C.c_void_p(f4.data_ptr()), C.c_void_p(u.data_ptr()), nrhs, sig, self._aligned(ws),
                     _stream_ptr(stream), C.byref(info))
+        # converged: None when not checked (ir_tol = 0, a fixed sweep count)
         self.last_info = dict(sweeps=info.sweeps, last_correction=info.last_correction,
-                              converged=bool(info.converged))
+                              converged=None if info.converged < 0 else bool(info.converged))
         if not (allow_unconverged and st == _lib.HELM_ENOTCONVERGED):
             check(st, "helm_solve")
         return u[0] if squeeze else u

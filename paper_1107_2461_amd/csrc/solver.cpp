@@ -15,7 +15,9 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <optional>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/helm.h"
@@ -225,6 +227,35 @@ void give_pinned_norms(unsigned long long* b) {
   std::lock_guard<std::mutex> lk(g_pin_mu);
   g_pin_pool.push_back(b);
 }
+// Waits for the work enqueued on `st` so far by spinning on an event: a refinement sweep ends
+// with a 16-byte norm copy the host needs at once, and a blocking stream synchronisation adds
+// tens of microseconds of wake-up latency to every sweep.  One event per host thread and
+// device, created on first use (the default system-scope release makes the pinned norms
+// visible when the event completes).
+hipError_t wait_stream(hipStream_t st) {
+  struct ThreadEvent {
+    int device = -1;
+    hipEvent_t ev = nullptr;
+    ~ThreadEvent() {
+      if (ev) (void)hipEventDestroy(ev);
+    }
+  };
+  thread_local ThreadEvent te;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (te.device != dev) {
+    if (te.ev) (void)hipEventDestroy(te.ev);
+    te.ev = nullptr;
+    te.device = -1;
+    if ((e = hipEventCreateWithFlags(&te.ev, hipEventDisableTiming)) != hipSuccess) return e;
+    te.device = dev;
+  }
+  if ((e = hipEventRecord(te.ev, st)) != hipSuccess) return e;
+  while ((e = hipEventQuery(te.ev)) == hipErrorNotReady) std::this_thread::yield();
+  return e;
+}
+
 struct PinnedNorms {
   unsigned long long* p = take_pinned_norms();
   ~PinnedNorms() { give_pinned_norms(p); }
@@ -339,7 +370,7 @@ static bool valid_opts(const helm_opts& o) {
   if (o.precision < HELM_FP64 || o.precision > HELM_BF16X3_IR) return false;
   if (o.method != HELM_TPF && o.method != HELM_TPT_Z) return false;
   if (o.null_mode != HELM_NULL_PROJECT && o.null_mode != HELM_NULL_PAPER_EQ28) return false;
-  if (!(o.ir_tol > 0.0) || o.max_sweeps < 1) return false;
+  if (!(o.ir_tol >= 0.0) || o.max_sweeps < 1) return false;
   // The Thomas path runs in FP64 only.
   if (o.method == HELM_TPT_Z && o.precision != HELM_FP64) return false;
   return true;
@@ -732,8 +763,13 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   }
   if (e != hipSuccess) return from_hip(e);
   if (!p->refined()) return from_hip(project_null());
-  PinnedNorms hn;  // pinned host copy of the norm stripes, from a process-wide pool
-  if (!hn.p) return HELM_ENOMEM;
+  // ir_tol = 0: a fixed sweep count with no norm read back (nothing allocated, nothing waited on)
+  const bool fixed = p->opts.ir_tol == 0.0;
+  std::optional<PinnedNorms> hn;  // pinned host copy of the norm stripes, from a process-wide pool
+  if (!fixed) {
+    hn.emplace();
+    if (!hn->p) return HELM_ENOMEM;
+  }
   int sweeps = 1;
   double last = 0.0, prev = 1.0;  // the first solve's "correction" is u itself
   bool conv = false;
@@ -747,20 +783,21 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
         return u0 ? stencil_u32(1, u0, f, L1, store, sz, st) : stencil(1, u, f, L1, store, sz, st);
       });
     if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st, false, false, u0);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hn.p, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
+    if (e == hipSuccess && !fixed)
+      e = hipMemcpyAsync(hn->p, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && !fixed) e = wait_stream(st);
     if (e != hipSuccess) return from_hip(e);
     ++sweeps;
+    if (fixed) continue;
     last = 0.0;
     bool finite = true;
     for (int r = 0; r < nrhs; ++r) {
       // the stripes hold non-negative FP64 bit patterns (NaN as the largest): integer max
       unsigned long long bd = 0, bu = 0;
       for (int q = 0; q < kNormStripes; ++q) {
-        bd = std::max(bd, hn.p[(2 * r) * kNormStripes + q]);
-        bu = std::max(bu, hn.p[(2 * r + 1) * kNormStripes + q]);
+        bd = std::max(bd, hn->p[(2 * r) * kNormStripes + q]);
+        bu = std::max(bu, hn->p[(2 * r + 1) * kNormStripes + q]);
       }
       double dm, um;
       std::memcpy(&dm, &bd, 8);
@@ -788,11 +825,11 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
   }
   if (info) {
     info->sweeps = sweeps;
-    info->last_correction = last;
-    info->converged = conv ? 1 : 0;
+    info->last_correction = fixed ? -1.0 : last;
+    info->converged = fixed ? -1 : (conv ? 1 : 0);
   }
   if ((e = project_null()) != hipSuccess) return from_hip(e);
-  return conv ? HELM_OK : HELM_ENOTCONVERGED;
+  return (conv || fixed) ? HELM_OK : HELM_ENOTCONVERGED;
 }
 
 extern "C" helm_status helm_pressure_setup(const helm_grid* grid, const helm_opts* opts, helm_plan** out) {
