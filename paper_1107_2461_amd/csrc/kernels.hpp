@@ -8,6 +8,13 @@
 
 namespace helm {
 
+// Waits for the work enqueued on `st` so far by spinning (with yields) on an event: the host
+// needs refinement norms, Krylov scalars or a finished request at once, and a blocking stream
+// synchronisation adds tens of microseconds of wake-up latency each time.  One event per host
+// thread and device, created on first use; its default system-scope release makes device
+// writes to pinned host memory visible when it completes.
+hipError_t wait_stream(hipStream_t st);
+
 // Storage / compute types of the mode products.
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 /* split BF16, FP32 storage */ };
 

@@ -126,7 +126,7 @@ helm_status dots(helm_pmat* pm, const double* V, int k, const double* w, unsigne
   double* dd = reinterpret_cast<double*>(ws + L.dots);
   hipError_t e = multi_dot(V, pm->np, k, w, pm->np, partial, dd, st);
   if (e == hipSuccess) e = hipMemcpyAsync(pm->host, dd, k * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = helm::wait_stream(st);
   if (e != hipSuccess) return st_from(e);
   std::memcpy(out, pm->host, k * sizeof(double));
   return HELM_OK;
@@ -140,7 +140,7 @@ helm_status axpys(helm_pmat* pm, double* w, const double* V, int k, const double
   std::memcpy(pm->host, c, k * sizeof(double));
   hipError_t e = hipMemcpyAsync(coef, pm->host, k * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = multi_axpy(w, V, pm->np, k, coef, pm->np, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = helm::wait_stream(st);
   return st_from(e);
 }
 

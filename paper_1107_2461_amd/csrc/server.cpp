@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
+#include "kernels.hpp"
 
 namespace {
 
@@ -182,7 +183,7 @@ struct helm_server {
     std::vector<helm_status> out(reqs.size(), HELM_OK);
     auto one = [&](Request& q) -> helm_status {
       helm_status st = helm_solve(q.plan.get(), q.f, q.u, q.nrhs, q.sigma.data(), s.ws, s.stream, &info);
-      if (st == HELM_OK && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
+      if (st == HELM_OK && helm::wait_stream(s.stream) != hipSuccess) st = HELM_EDEVICE;
       return st;
     };
     if (reqs.size() == 1) {
@@ -220,7 +221,7 @@ struct helm_server {
         o += q->nrhs;
       }
     }
-    if ((st == HELM_OK || st == HELM_ENOTCONVERGED) && hipStreamSynchronize(s.stream) != hipSuccess) st = HELM_EDEVICE;
+    if ((st == HELM_OK || st == HELM_ENOTCONVERGED) && helm::wait_stream(s.stream) != hipSuccess) st = HELM_EDEVICE;
     std::fill(out.begin(), out.end(), st);
     return out;
   }

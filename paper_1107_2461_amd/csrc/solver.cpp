@@ -227,11 +227,14 @@ void give_pinned_norms(unsigned long long* b) {
   std::lock_guard<std::mutex> lk(g_pin_mu);
   g_pin_pool.push_back(b);
 }
-// Waits for the work enqueued on `st` so far by spinning on an event: a refinement sweep ends
-// with a 16-byte norm copy the host needs at once, and a blocking stream synchronisation adds
-// tens of microseconds of wake-up latency to every sweep.  One event per host thread and
-// device, created on first use (the default system-scope release makes the pinned norms
-// visible when the event completes).
+struct PinnedNorms {
+  unsigned long long* p = take_pinned_norms();
+  ~PinnedNorms() { give_pinned_norms(p); }
+};
+
+}  // namespace
+
+namespace helm {
 hipError_t wait_stream(hipStream_t st) {
   struct ThreadEvent {
     int device = -1;
@@ -255,13 +258,7 @@ hipError_t wait_stream(hipStream_t st) {
   while ((e = hipEventQuery(te.ev)) == hipErrorNotReady) std::this_thread::yield();
   return e;
 }
-
-struct PinnedNorms {
-  unsigned long long* p = take_pinned_norms();
-  ~PinnedNorms() { give_pinned_norms(p); }
-};
-
-}  // namespace
+}  // namespace helm
 
 // Optional per-launch event timing (helm_profile_enable / helm_profile_read).
 struct StageProfiler {
@@ -786,7 +783,7 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
     if (e == hipSuccess && !fixed)
       e = hipMemcpyAsync(hn->p, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && !fixed) e = wait_stream(st);
+    if (e == hipSuccess && !fixed) e = helm::wait_stream(st);
     if (e != hipSuccess) return from_hip(e);
     ++sweeps;
     if (fixed) continue;
