@@ -260,14 +260,15 @@ def committed_traffic(prec, stage):
     return ent.get("bytes_per_launch")
 
 
-def run_pressure_matrix(torch, prob, f, tau, precision, steps):
-    """FGMRES(30) on the pressure matrix C of eq. 9 (velocity Helmholtz plans with sigma = 1/tau),
-    to a 1e-10 relative residual, without and with the two preconditioners."""
+def run_pressure_matrix(torch, prob, f, tau, precision, steps, method="tpf", pcs=(0, 1, 2)):
+    """FGMRES(30) on the pressure matrix C of eq. 9 (velocity Helmholtz plans with sigma = 1/tau,
+    TPF or TPT), to a 1e-10 relative residual, without and with the two preconditioners."""
     from paper_1107_2461_amd import PressureMatrix
-    pm = PressureMatrix(prob.faces, tau, precision=precision)
+    pm = PressureMatrix(prob.faces, tau, precision=precision, method=method)
     b = torch.from_numpy(f[0]).cuda()
     out = {}
-    for pc, name in ((0, "none"), (1, "pressure_laplacian"), (2, "cahouet_chabard")):
+    names = {0: "none", 1: "pressure_laplacian", 2: "cahouet_chabard"}
+    for pc, name in ((pc, names[pc]) for pc in pcs):
         pm.solve(b, tol=1e-10, max_it=500, restart=30, precondition=pc)   # warm-up (plans, workspace)
         torch.cuda.synchronize()
         ts = []
@@ -280,7 +281,7 @@ def run_pressure_matrix(torch, prob, f, tau, precision, steps):
         r = float((b - pm.apply(p)).norm() / b.norm())
         out[name] = dict(iterations=info["iterations"], converged=bool(info["converged"]), rel_residual=r,
                          ms_per_solve=1e3 * float(np.median(ts)))
-        log(f"[bench] FGMRES precond={name}: {info['iterations']} it, res {r:.2e}, "
+        log(f"[bench] FGMRES {method} precond={name}: {info['iterations']} it, res {r:.2e}, "
             f"{out[name]['ms_per_solve']:.1f} ms")
     del pm
     return out
@@ -304,6 +305,8 @@ def run_pressure(torch, args):
     b = results[best]
     d = b["dominant"]
     fg = run_pressure_matrix(torch, prob, f, 1e2, "fp64", max(1, min(args.steps, 3)))
+    fg["tpt"] = run_pressure_matrix(torch, prob, f, 1e2, "fp64", max(1, min(args.steps, 3)), method="tpt",
+                                    pcs=(0, 2))
     line = dict(metric="grid-pts/s per pressure (all-Neumann) solve @1e-10 rel err", value=b["pts_per_s"],
                 unit="grid-pts/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=b["ms_per_step"],
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype=b["precision"], data="synthetic",

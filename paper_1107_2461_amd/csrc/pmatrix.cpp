@@ -170,7 +170,7 @@ extern "C" helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, c
   helm_opts vo;
   helm_default_opts(&vo);
   if (opts) vo = *opts;
-  vo.method = HELM_TPF;
+  if (vo.precision != HELM_FP64) vo.method = HELM_TPF;  // the Thomas variant runs in FP64 only
   for (int d = 0; d < 3; ++d) {
     helm_grid g = *p_grid;
     for (int e = 0; e < 3; ++e) g.loc[e] = (e == d) ? HELM_FACE : HELM_CELL;

@@ -29,11 +29,12 @@ def _faces(n, betas=(1.5, 1.0, 2.0)):
     return tuple(workloads.stretched_faces(n[d], betas[d]) for d in range(3))
 
 
+@pytest.mark.parametrize("method", ["tpf", "tpt"])
 @pytest.mark.parametrize("n,tau", [((9, 7, 11), 1e2), ((12, 10, 8), 1e-2), ((6, 13, 7), 1.0)])
-def test_pmatrix_apply_matches_oracle(torch, n, tau):
+def test_pmatrix_apply_matches_oracle(torch, n, tau, method):
     from paper_1107_2461_amd import PressureMatrix
     faces = _faces(n)
-    pm = PressureMatrix(faces, tau)
+    pm = PressureMatrix(faces, tau, method=method)
     orc = pressure.PressureMatrix(faces, 1.0 / tau)
     rng = np.random.default_rng(8)
     for _ in range(2):
@@ -43,8 +44,8 @@ def test_pmatrix_apply_matches_oracle(torch, n, tau):
         assert solvers.rel_err(y, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16_ir"])
-def test_pmatrix_fgmres_matches_dense_oracle(torch, precision):
+@pytest.mark.parametrize("precision,method", [("fp64", "tpf"), ("fp64", "tpt"), ("bf16_ir", "tpf")])
+def test_pmatrix_fgmres_matches_dense_oracle(torch, precision, method):
     from paper_1107_2461_amd import PressureMatrix
     n = (10, 8, 12)
     faces = _faces(n)
@@ -53,7 +54,7 @@ def test_pmatrix_fgmres_matches_dense_oracle(torch, precision):
     orc = pressure.PressureMatrix(faces, 1.0 / tau)
     ref, mu = orc.solve_dense_gauged(b.ravel())
     assert abs(mu) < 1e-8
-    pm = PressureMatrix(faces, tau, precision=precision)
+    pm = PressureMatrix(faces, tau, precision=precision, method=method)
     p = pm.solve(torch.from_numpy(b).cuda(), tol=1e-11, max_it=300, restart=30).cpu().numpy().ravel()
     info = pm.last_info
     assert info["converged"], info
