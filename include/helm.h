@@ -158,8 +158,9 @@ helm_status helm_pressure_solve(helm_plan* plan, const double* f, double* p, int
 /* Pressure matrix C of eq. 9 on a MAC grid: C p = -sum_d Div_d H_d^{-1} Grad_d p with
  * H_d = (1/tau) I - Lap_h on the d-velocity grid (no-slip walls) and no pressure
  * boundary values.  p_grid gives the pressure cells (loc ignored); the three velocity
- * plans use opts->precision for their Helmholtz solves; the preconditioner is the
- * pressure Laplacian (the Chorin limit of C, end of Section 2).  Errors as helm_setup. */
+ * plans use opts->precision for their Helmholtz solves, and opts->method when the precision
+ * is FP64 (the Thomas variant is FP64 only; other precisions use TPF); the preconditioner is
+ * the pressure Laplacian (the Chorin limit of C, end of Section 2).  Errors as helm_setup. */
 helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, const helm_opts* opts,
                                helm_pmat** out);
 
