@@ -452,6 +452,12 @@ PROFILE_COMMANDS = (
 PROFILE_TRACE_128 = ("rocprofv3 --kernel-trace --stats --output-format csv -d {d}/kt128 -o kt -- "
                      "python -u bench.py --workload multirhs_128 --steps 5 --warmup 1 --no-cpu-baseline "
                      "--paths fp64,tpt,bf16x3_ir")
+# HBM traffic of the Thomas pass (TPT, 128^3 x 3 RHS), one counter per run, with the same copy
+# calibration as the 256^3 runs.
+PROFILE_TRAFFIC_128 = tuple(
+    f"rocprofv3 --pmc {c} --output-format csv -d {{d}}/{t}128 -o {t[0]} -- "
+    "python -u bench.py --workload multirhs_128 --steps 2 --warmup 0 --no-cpu-baseline --paths tpt "
+    "--copy-ref-mb 1024" for c, t in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")))
 # (path family, stage) -> (kernel name prefix in the trace, algorithmic bytes per point)
 TRAFFIC_STAGES = {
     ("bf16x3", "z_fwd_div"): ("void helm::k_rot_bf16x3<4, 4, 8, 1, true, float>", 8),
@@ -566,6 +572,38 @@ def summarize_profiles(d, copy_mb=1024, npts=256 ** 3, workload="256^3 Helmholtz
                              f"{fl / 1e12:.4f} | {fl / alg:.2f} |"))
         lines += [r for _, r in sorted(rows, key=lambda t: -t[0])]
         with open(os.path.join(prof_dir, "mfma_util_helmholtz_256cube.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    # Thomas pass: bytes per launch against its algorithmic and designed traffic
+    t_per = {}
+    for tag, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        rows = [r for r in _read_csv(os.path.join(d, tag + "128", "**", "*counter_collection.csv"))
+                if r["Counter_Name"] == counter]
+        vals = collections.defaultdict(list)
+        for r in rows:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        copies = [v for k, vs in vals.items() if "copyBuffer" in k for v in vs]
+        th = [v for k, vs in vals.items() if k.startswith("helm::k_thomas") for v in vs]
+        if copies and th:
+            t_per[tag] = sum(th) / len(th) * 1024.0 * (copy_mb * 1024.0 / max(copies))
+    t_stats = [r for r in _read_csv(os.path.join(d, "kt128", "**", "*kernel_stats.csv"))
+               if r["Name"].startswith("helm::k_thomas")]
+    if len(t_per) == 2 and t_stats:
+        pts = 3 * 128 ** 3
+        avg_s = float(t_stats[0]["AverageNs"]) * 1e-9
+        tot = t_per["fetch"] + t_per["write"]
+        lines = ["# HBM traffic of the Thomas pass, 128^3 x 3 RHS (TPT)", "",
+                 "Counter runs (repo root, one MI355X), and the trace that gives the kernel duration:", "",
+                 "```"] + [c.format(d=d) for c in PROFILE_TRAFFIC_128] + [PROFILE_TRACE_128.format(d=d), "```", "",
+                 "Bytes = counter KiB x 1024, scaled by the 1 GiB copy in the same run (L2-miss bytes, an upper",
+                 "bound on HBM bytes).  Algorithmic: read g and write v once (16 B/point); the kernel reads each",
+                 "line twice and writes it once (24 B/point) plus 1 B/point of checkpoints.", "",
+                 "| read MB | write MB | total MB | algorithmic MB (16 B) | designed MB (24 B) | avg us | algorithmic GB/s | "
+                 "measured GB/s | of 8 TB/s |",
+                 "|---:|---:|---:|---:|---:|---:|---:|---:|---:|",
+                 f"| {t_per['fetch'] / 1e6:.1f} | {t_per['write'] / 1e6:.1f} | {tot / 1e6:.1f} | {16 * pts / 1e6:.1f} | "
+                 f"{24 * pts / 1e6:.1f} | {avg_s * 1e6:.1f} | {16 * pts / avg_s / 1e9:.0f} | {tot / avg_s / 1e9:.0f} | "
+                 f"{tot / avg_s / 8e12:.2f} |"]
+        with open(os.path.join(prof_dir, "hbm_traffic_thomas_128cube_x3.md"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
     log(f"[bench] profiles written from {d}")
 
