@@ -620,8 +620,8 @@ def _hash_files(rels):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="mixed_256",
                     help="mixed_256 (default), multirhs_128, small_32, pressure, serving")
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
