@@ -58,7 +58,12 @@ def _stream_ptr(stream):
 
 
 class Plan:
-    """A solve plan for (sigma I - Lap_h) u = f (helm_setup)."""
+    """A solve plan for (sigma I - Lap_h) u = f (helm_setup).
+
+    precision: "fp64", "fp32", "bf16", "bf16x3" or their "_ir" forms (refined in FP64);
+    method: "tpf" or "tpt" (Thomas in z, FP64); ir_tol / max_sweeps: refinement stop (the
+    library's defaults when None); ir_tol = 0 runs exactly max_sweeps sweeps without reading
+    norms back, so a solve only enqueues kernels and may be captured in a CUDA graph."""
 
     def __init__(self, faces, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, sigma=0.0, loc=(CELL,) * 3,
                  precision="fp64", method="tpf", ir_tol=None, max_sweeps=None, null_mode=NULL_PROJECT,
