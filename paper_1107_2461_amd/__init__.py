@@ -230,10 +230,13 @@ def host_eigen_1d(faces, loc=CELL, bc_lo=DIRICHLET, bc_hi=DIRICHLET):
 class PressureMatrix:
     """Pressure matrix C of eq. 9 with FGMRES solve (helm_pmatrix_*)."""
 
-    def __init__(self, faces, tau, precision="fp64", method="tpf"):
-        """method: "tpf" or "tpt" (FP64 only) for the velocity and pressure-preconditioner solves."""
+    def __init__(self, faces, tau, precision="fp64", method=None):
+        """method: "tpf" or "tpt" (FP64 only) for the velocity and pressure-preconditioner solves;
+        None picks the Thomas variant in FP64 (the faster one there) and "tpf" otherwise."""
         lib = load()
         g, self._faces = _grid(faces, (CELL,) * 3)
+        if method is None:
+            method = "tpt" if precision == "fp64" else "tpf"
         opts = _opts(precision, method, None, None, NULL_PROJECT)
         h = C.c_void_p()
         check(lib.helm_pmatrix_setup(C.byref(g), float(tau), C.byref(opts), C.byref(h)), "helm_pmatrix_setup")
