@@ -127,6 +127,12 @@ __device__ inline double divide_den(double v, const EpiArgs& ep, double den) {
   if (den == 0.0) return ep.eq28 ? v : 0.0;
   return v * recip(den);
 }
+// The same as a select: an epilogue that divides then has no control-flow joins between its
+// stores, where a wait for an earlier load would also wait for every store issued so far.
+__device__ inline double divide_den_sel(double v, const EpiArgs& ep, double den) {
+  const double q = v * recip(den);
+  return den == 0.0 ? (ep.eq28 ? v : 0.0) : q;
+}
 __device__ inline double divide_by_eigs(double v, const EpiArgs& ep, int c, double shift) {
   return divide_den(v, ep, ep.lamz[c] + shift);
 }
@@ -200,6 +206,16 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   const long long total = S * Nn;
   const long long c0 = static_cast<long long>(blockIdx.x) * NT + wn * NB * 16;
   const int rb0 = wm * MB;
+  // FP64 divide: lambda_z of every output row staged in LDS before the main loop, so the
+  // epilogue reads no global memory between its stores (FP32 keeps the registers of kPre below,
+  // measured faster there)
+  constexpr bool kLds = EPI == EPI_DIVIDE && std::is_same<TC, double>::value;
+  constexpr int NLZ = kLds ? W * MB * 16 : 1;
+  [[maybe_unused]] __shared__ double sh_lz[NLZ];
+  if constexpr (kLds) {
+    for (int a = threadIdx.x; a < NLZ; a += blockDim.x) sh_lz[a] = a < K ? ep.lamz[a] : 1.0;
+    __syncthreads();
+  }
 
   long long base[NB];
   bool colok[NB];
@@ -255,10 +271,10 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
         for (int s = 0; s < 4; ++s) b_cur[nb][s] = b_nxt[nb][s];
     }
   }
-  // eigenvalues of the lane's rows, all loaded before the first store (the vector-memory
-  // counter also counts stores: a load issued after a store would wait for it); the widest
-  // entry (NB = 8, K <= 32) has no registers to spare and loads them at the store
-  constexpr bool kPre = EPI == EPI_DIVIDE && NB <= 4;
+  // FP32 divide: eigenvalues of the lane's rows, all loaded before the first store (the vector-
+  // memory counter also counts stores: a load issued after a store would wait for it); the
+  // widest entry (NB = 8, K <= 32) has no registers to spare and loads them at the store
+  constexpr bool kPre = EPI == EPI_DIVIDE && !kLds && NB <= 4;
   [[maybe_unused]] double lz[kPre ? MB : 1][4];
   if constexpr (kPre) {
 #pragma unroll
@@ -279,8 +295,12 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
         if (a >= K || !colok[nb]) continue;
         const long long idx = base[nb] + static_cast<long long>(a) * Nn;
         if constexpr (EPI == EPI_DIVIDE) {
-          const double lza = kPre ? lz[kPre ? mb : 0][r] : ep.lamz[a];
-          Y[idx] = store_cvt<TC>(divide_den(static_cast<double>(acc[mb][nb][r]), ep, lza + den_xy[nb]));
+          if constexpr (kLds) {
+            Y[idx] = store_cvt<TC>(divide_den_sel(static_cast<double>(acc[mb][nb][r]), ep, sh_lz[a] + den_xy[nb]));
+          } else {
+            const double lza = kPre ? lz[kPre ? mb : 0][r] : ep.lamz[a];
+            Y[idx] = store_cvt<TC>(divide_den(static_cast<double>(acc[mb][nb][r]), ep, lza + den_xy[nb]));
+          }
         } else {
           Y[idx] = static_cast<TC>(acc[mb][nb][r]);
         }
