@@ -14,6 +14,7 @@ Modules
   fv        grid geometry, 1D operators, 3D cell-by-cell assembly, MAC div/grad
   solvers   dense LU, sparse LU, Jacobi-PCG on the SPD form, Neumann gauge handling
   pressure  the pressure matrix C of eq. 9 (dense at small sizes, and its action)
+  stokes    the Stokes system of eq. 8, assembled and bordered, solved by sparse LU
 
 Every function here is pinned by the CPU tests (tests/test_oracle_*.py) against
 closed forms, library transforms, brute force and hand-computed fixtures.
