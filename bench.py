@@ -287,6 +287,59 @@ def run_pressure_matrix(torch, prob, f, tau, precision, steps, method="tpf", pcs
     return out
 
 
+def stokes_rows(torch, faces, tau, u, p, f):
+    """Relative residuals of the rows of eq. 8 for a GPU Stokes result: momentum rows with the
+    velocity plans' FP64 operator (helm_apply) plus the pressure difference, continuity as the
+    MAC divergence with zero wall velocities (torch differences; a check, not the solve)."""
+    from paper_1107_2461_amd import CELL, FACE, Plan
+    import torch.nn.functional as F
+    mom, div, dscale = 0.0, torch.zeros_like(p), 0.0
+    for d in range(3):
+        fc = np.asarray(faces[d], dtype=np.float64)
+        c, w = 0.5 * (fc[1:] + fc[:-1]), np.diff(fc)
+        loc = [CELL] * 3
+        loc[d] = FACE
+        Hu = Plan(faces, sigma=1.0 / tau, loc=tuple(loc)).apply(u[d])
+        axis = 2 - d                                   # tensors are (z, y, x)
+        shape = [1, 1, 1]
+        shape[axis] = -1
+        inv_dc = torch.from_numpy(1.0 / np.diff(c)).cuda().view(shape)
+        mom = max(mom, float((Hu + torch.diff(p, dim=axis) * inv_dc - f[d]).abs().max() / f[d].abs().max()))
+        pad = [0] * 6
+        pad[2 * d], pad[2 * d + 1] = 1, 1              # F.pad lists the last dimension (x) first
+        inv_w = torch.from_numpy(1.0 / w).cuda().view(shape)
+        div += torch.diff(F.pad(u[d], pad), dim=axis) * inv_w
+        dscale = max(dscale, float(u[d].abs().max()) / float(w.min()))
+    return mom, float(div.abs().max()) / dscale
+
+
+def run_stokes(torch, prob, tau, precision, steps, method="tpt"):
+    """One Stokes solve of eq. 8 by the three steps of Section 2 (six velocity solves and FGMRES(30)
+    with the Cahouet-Chabard preconditioner to 1e-10) on the pressure grid's MAC mesh; the forcing
+    is seeded U[-1, 1] on the three velocity grids, g = 0 (the paper's continuity row)."""
+    from paper_1107_2461_amd import PressureMatrix
+    pm = PressureMatrix(prob.faces, tau, precision=precision, method=method)
+    rng = np.random.default_rng(4)
+    f = [torch.from_numpy(rng.uniform(-1, 1, s)).cuda() for s in pm.velocity_shapes()]
+    pm.stokes(f, tol=1e-10, max_it=500, restart=30, precondition=2)   # warm-up (plans, workspace)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        out = pm.stokes(f, tol=1e-10, max_it=500, restart=30, precondition=2)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    info = pm.last_info
+    mom, div = stokes_rows(torch, prob.faces, tau, out[:3], out[3], f)
+    res = dict(precision=precision, method=method, iterations=info["iterations"], converged=bool(info["converged"]),
+               fgmres_rel_residual=info["residual"], momentum_rel_residual=mom, continuity_rel_residual=div,
+               ms_per_solve=1e3 * float(np.median(ts)))
+    log(f"[bench] Stokes {precision}/{method}: {info['iterations']} it, rows {mom:.1e} / {div:.1e}, "
+        f"{res['ms_per_solve']:.1f} ms")
+    del pm
+    return res
+
+
 def run_pressure(torch, args):
     """The pressure workload: all-Neumann pressure Laplacian solves (eq. 28) and FGMRES on the
     pressure matrix C (eq. 9) with tau = 100."""
@@ -307,6 +360,7 @@ def run_pressure(torch, args):
     fg = run_pressure_matrix(torch, prob, f, 1e2, "fp64", max(1, min(args.steps, 3)))
     fg["tpt"] = run_pressure_matrix(torch, prob, f, 1e2, "fp64", max(1, min(args.steps, 3)), method="tpt",
                                     pcs=(0, 2))
+    sk = run_stokes(torch, prob, 1e2, "fp64", max(1, min(args.steps, 3)))
     line = dict(metric="grid-pts/s per pressure (all-Neumann) solve @1e-10 rel err", value=b["pts_per_s"],
                 unit="grid-pts/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=b["ms_per_step"],
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype=b["precision"], data="synthetic",
@@ -315,7 +369,7 @@ def run_pressure(torch, args):
                 p50_ms=b["p50_ms"], p99_ms=b["p99_ms"],
                 roofline=dict(kernel=d["kernel"], bound=d["bound"], achieved=d["achieved"], peak=d["peak"],
                               unit=d["unit"], frac=d["frac"], traffic=None, avg_us=d["avg_us"]),
-                cpu_baseline=None, fgmres_tau100=fg,
+                cpu_baseline=None, fgmres_tau100=fg, stokes_tau100=sk,
                 paths={k: {kk: vv for kk, vv in v.items()} for k, v in results.items()})
     print(json.dumps(line))
 

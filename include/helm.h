@@ -184,6 +184,30 @@ helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double* p, double
 
 void helm_pmatrix_destroy(helm_pmat* pm);
 
+/* Workspace bytes for helm_stokes_solve with restart length m (the helm_pmatrix_solve
+ * workspace plus one pressure field and a reduction scratch). */
+helm_status helm_stokes_workspace_size(const helm_pmat* pm, int restart, size_t* bytes);
+
+/* Stokes system of eq. 8 (Section 2) on the MAC grid of pm, solved by the three steps that
+ * follow its LU factorization: velocity solves, the pressure-matrix solve, velocity solves.
+ * In the library's signs (the paper's momentum rows times -1, f_d = -R_d):
+ *     H_d u_d + Grad_d p = f_d  (d = x, y, z),     sum_d Div_d u_d = g,
+ * with H_d = (1/tau) I - Lap_h on the d-velocity grid and zero velocity on every wall.
+ *   f[d], u[d]: device FP64 fields on the d-velocity grid, the pressure cell counts with one
+ *               fewer along d, [nz'][ny'][nx'] x fastest; u[d] must not alias f[d], g, p or
+ *               another u.
+ *   g: device FP64 pressure-grid field, or NULL for 0 (the paper's case); its volume-weighted
+ *      mean is dropped (the part no wall-bounded velocity can produce).
+ *   p: device FP64 pressure-grid output with zero volume-weighted mean.
+ *   tol, max_it, restart, use_precond: as helm_pmatrix_solve for step 2.
+ *   ws: helm_stokes_workspace_size bytes, 256-byte aligned, owned by the caller.
+ * Costs six velocity solves plus the FGMRES iterations (three velocity solves each).
+ * Returns the first failing velocity solve's status, else helm_pmatrix_solve's (u is then
+ * computed from the best p); info gets the FGMRES iterations and relative residual. */
+helm_status helm_stokes_solve(helm_pmat* pm, const double* const f[3], const double* g,
+                              double* const u[3], double* p, double tol, int max_it, int restart,
+                              int use_precond, void* ws, void* stream, helm_info* info);
+
 /* Stage timing (a tracing aid).  When enabled on a plan, every kernel launch made by
  * helm_solve / helm_apply with that plan is bracketed by two HIP events recorded on the
  * call's stream, tagged with its stage below.  helm_profile_read synchronizes those events,

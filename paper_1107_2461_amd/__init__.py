@@ -284,6 +284,45 @@ class PressureMatrix:
             check(st, "helm_pmatrix_solve")
         return p
 
+    def velocity_shapes(self):
+        """(nz, ny, nx) of the x-, y- and z-velocity grids (one fewer node along their own axis)."""
+        nx, ny, nz = self.shape_xyz
+        return (nz, ny, nx - 1), (nz, ny - 1, nx), (nz - 1, ny, nx)
+
+    def stokes(self, f, g=None, tol=1e-10, max_it=500, restart=30, precondition=2, stream=None):
+        """Stokes system of eq. 8 by its three-step factorization (helm_stokes_solve):
+        H_d u_d + Grad_d p = f[d], sum_d Div_d u_d = g (None: 0).  f: three contiguous float64
+        CUDA tensors on the velocity grids (velocity_shapes()); returns (u_x, u_y, u_z, p) with p
+        of zero volume-weighted mean."""
+        torch = _torch()
+        lib = load()
+        for fd, shp in zip(f, self.velocity_shapes()):
+            if tuple(fd.shape) != shp or fd.dtype != torch.float64 or not fd.is_contiguous():
+                raise ValueError(f"velocity right-hand side must be contiguous float64 of shape {shp}")
+        if g is not None and (tuple(g.shape) != tuple(reversed(self.shape_xyz)) or g.dtype != torch.float64
+                              or not g.is_contiguous()):
+            raise ValueError("g must be a contiguous float64 field on the pressure cells (nz, ny, nx)")
+        key = ("stokes", restart)
+        ws = self._ws.get(key)
+        if ws is None:
+            n = C.c_size_t()
+            check(lib.helm_stokes_workspace_size(self._h, int(restart), C.byref(n)), "workspace")
+            ws = torch.empty(n.value + 256, dtype=torch.uint8, device=f[0].device)
+            self._ws[key] = ws
+        nx, ny, nz = self.shape_xyz
+        u = [torch.empty_like(fd) for fd in f]
+        p = torch.empty((nz, ny, nx), dtype=torch.float64, device=f[0].device)
+        fa = (C.c_void_p * 3)(*[fd.data_ptr() for fd in f])
+        ua = (C.c_void_p * 3)(*[ud.data_ptr() for ud in u])
+        info = _lib.HelmInfo()
+        st = lib.helm_stokes_solve(self._h, fa, C.c_void_p(g.data_ptr() if g is not None else None), ua,
+                                   C.c_void_p(p.data_ptr()), float(tol), int(max_it), int(restart), int(precondition),
+                                   Plan._aligned(ws), _stream_ptr(stream), C.byref(info))
+        self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK)
+        if st not in (_lib.HELM_OK, _lib.HELM_ENOTCONVERGED):
+            check(st, "helm_stokes_solve")
+        return u[0], u[1], u[2], p
+
 
 class Server:
     """Continuous-batching solve server (helm_server_*): submit requests, poll completions."""

@@ -73,6 +73,9 @@ SIGNATURES = {
     "helm_pmatrix_solve": (C.c_int, [P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P,
                                      C.POINTER(HelmInfo)]),
     "helm_pmatrix_destroy": (None, [P]),
+    "helm_stokes_workspace_size": (C.c_int, [P, C.c_int, C.POINTER(C.c_size_t)]),
+    "helm_stokes_solve": (C.c_int, [P, C.POINTER(P), P, C.POINTER(P), P, C.c_double, C.c_int, C.c_int, C.c_int, P, P,
+                                    C.POINTER(HelmInfo)]),
     "helm_profile_enable": (C.c_int, [P, C.c_int]),
     "helm_profile_read": (C.c_int, [P, DP, IP]),
     "helm_profile_stages": (C.c_int, [P, C.c_uint]),

@@ -49,6 +49,8 @@ struct helm_pmat {
   size_t vel_ws = 0, pres_ws = 0;
   double* inv_dc[3] = {nullptr, nullptr, nullptr};  // 1 / (c_{i+1} - c_i), n - 1
   double* inv_w[3] = {nullptr, nullptr, nullptr};   // 1 / w_i, n
+  double* wid[3] = {nullptr, nullptr, nullptr};     // w_i, n (volume weights of the gauge)
+  double inv_volsum = 0.0;                          // 1 / (domain volume)
   double* host = nullptr;                           // pinned scratch (dots, coefficients)
   int device = 0;
   ~helm_pmat() {
@@ -56,6 +58,7 @@ struct helm_pmat {
       if (vel[d]) helm_destroy(vel[d]);
       if (inv_dc[d]) (void)hipFree(inv_dc[d]);
       if (inv_w[d]) (void)hipFree(inv_w[d]);
+      if (wid[d]) (void)hipFree(wid[d]);
     }
     if (pres) helm_destroy(pres);
     if (host) (void)hipHostFree(host);
@@ -186,18 +189,28 @@ extern "C" helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, c
   helm_status s = helm_pressure_setup(p_grid, &vo, &pm->pres);
   if (s != HELM_OK) return s;
   if ((s = helm_workspace_size(pm->pres, 1, &pm->pres_ws)) != HELM_OK) return s;
+  double volsum = 1.0;
   for (int d = 0; d < 3; ++d) {
     const int n = pm->n[d];
     const double* f = p_grid->faces[d];
-    std::vector<double> idc(n - 1), iw(n);
-    for (int i = 0; i < n; ++i) iw[i] = 1.0 / (f[i + 1] - f[i]);
+    std::vector<double> idc(n - 1), iw(n), wd(n);
+    double len = 0.0;
+    for (int i = 0; i < n; ++i) {
+      wd[i] = f[i + 1] - f[i];
+      iw[i] = 1.0 / wd[i];
+      len += wd[i];
+    }
+    volsum *= len;
     for (int i = 0; i + 1 < n; ++i) idc[i] = 1.0 / (0.5 * (f[i + 2] - f[i]));  // c_{i+1} - c_i
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&pm->inv_dc[d]), (n - 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pm->inv_w[d]), n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pm->wid[d]), n * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(pm->inv_dc[d], idc.data(), (n - 1) * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(pm->inv_w[d], iw.data(), n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pm->wid[d], wd.data(), n * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return st_from(e);
   }
+  pm->inv_volsum = 1.0 / volsum;
   if (hipHostMalloc(reinterpret_cast<void**>(&pm->host), (kMaxRestart + 2) * sizeof(double)) != hipSuccess)
     return HELM_ENOMEM;
   *out = pm.release();
@@ -350,6 +363,90 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
     info->converged = relres <= tol;
   }
   return relres <= tol ? HELM_OK : HELM_ENOTCONVERGED;
+}
+
+// ---- Stokes system (Section 2, eq. 8) by the three-step factorization ----
+// With the momentum rows in the library's sign (H_d u_d + Grad_d p = f_d, sum_d Div_d u_d = g):
+//   1. u^_d = H_d^{-1} f_d                       (three velocity solves)
+//   2. C p = g - sum_d Div_d u^_d                 (FGMRES on the pressure matrix)
+//   3. u_d = u^_d - H_d^{-1} Grad_d p             (three more velocity solves)
+// The velocities vanish on the walls, so Div u^ has zero volume-weighted mean and the
+// right-hand side of step 2 is compatible once that mean is removed from g.
+namespace {
+struct StokesLayout {
+  PmLayout pm;
+  size_t b, mean, total;
+};
+StokesLayout stokes_layout(const helm_pmat* pm, int m) {
+  StokesLayout L{};
+  L.pm = pm_layout(pm, m);
+  size_t t = L.pm.total;
+  L.b = t;
+  t += align256(pm->np * 8);
+  L.mean = t;
+  t += align256((kMeanBlocks + 1) * 8);
+  L.total = t;
+  return L;
+}
+}  // namespace
+
+extern "C" helm_status helm_stokes_workspace_size(const helm_pmat* pm, int restart, size_t* bytes) {
+  if (!pm || !bytes || restart < 1 || restart > kMaxRestart) return HELM_EINVAL;
+  *bytes = stokes_layout(pm, restart).total;
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_stokes_solve(helm_pmat* pm, const double* const f[3], const double* g,
+                                         double* const u[3], double* p, double tol, int max_it, int restart,
+                                         int use_precond, void* wsv, void* stream, helm_info* info) {
+  if (!pm || !f || !u || !p || !wsv || !(tol > 0.0) || max_it < 1 || restart < 1 || restart > kMaxRestart)
+    return HELM_EINVAL;
+  if (use_precond < 0 || use_precond > 2 || reinterpret_cast<uintptr_t>(wsv) % 256) return HELM_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (!f[d] || !u[d] || f[d] == u[d] || u[d] == p || static_cast<const double*>(u[d]) == g) return HELM_EINVAL;
+    for (int e = 0; e < d; ++e)
+      if (u[e] == u[d]) return HELM_EINVAL;
+  }
+  if (g == p) return HELM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* ws = static_cast<unsigned char*>(wsv);
+  const StokesLayout L = stokes_layout(pm, restart);
+  double* b = reinterpret_cast<double*>(ws + L.b);
+  helm_status s = HELM_OK;
+  // 1. u^ = H^{-1} f, held in u
+  for (int d = 0; d < 3 && s == HELM_OK; ++d) {
+    helm_info vi;
+    s = helm_solve(pm->vel[d], f[d], u[d], 1, nullptr, ws + L.pm.velws, st, &vi);
+  }
+  if (s != HELM_OK) return s;
+  // 2. b = P_V (g - sum Div u^), then C p = b
+  hipError_t e = g ? scale(b, g, 1.0, pm->np, st) : fill(b, pm->np, 0.0, st);
+  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = mac_div_acc(d, u[d], b, pm->n, pm->inv_w[d], -1.0, st);
+  if (e == hipSuccess)
+    e = remove_mean(b, pm->wid[0], pm->wid[1], pm->wid[2], pm->n[0], pm->n[1], pm->n[2], 1, pm->inv_volsum, 1ull,
+                    reinterpret_cast<double*>(ws + L.mean), st);
+  if (e != hipSuccess) return st_from(e);
+  helm_info ci;
+  const helm_status sc = helm_pmatrix_solve(pm, b, p, tol, max_it, restart, use_precond, wsv, stream, &ci);
+  if (sc != HELM_OK && sc != HELM_ENOTCONVERGED) return sc;
+  // 3. u -= H^{-1} Grad p
+  for (int d = 0; d < 3 && s == HELM_OK; ++d) {
+    double* gv = reinterpret_cast<double*>(ws + L.pm.g[d]);
+    double* t = reinterpret_cast<double*>(ws + L.pm.vs[d]);
+    if ((e = mac_grad(d, p, gv, pm->n, pm->inv_dc[d], st)) != hipSuccess) return st_from(e);
+    helm_info vi;
+    s = helm_solve(pm->vel[d], gv, t, 1, nullptr, ws + L.pm.velws, st, &vi);
+    if (s == HELM_OK && (e = axpby(u[d], 1.0, t, -1.0, pm->nv[d], st)) != hipSuccess) return st_from(e);
+  }
+  if (s != HELM_OK) return s;
+  if (info) {
+    info->iterations = ci.iterations;
+    info->residual = ci.residual;
+    info->converged = ci.converged;
+    info->sweeps = 0;
+    info->last_correction = 0.0;
+  }
+  return sc;
 }
 
 extern "C" void helm_pmatrix_destroy(helm_pmat* pm) {

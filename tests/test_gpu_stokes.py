@@ -1,0 +1,107 @@
+"""GPU parity of the Stokes solve (eq. 8 by the three steps of Section 2, helm_stokes_solve).
+
+The oracle solves the assembled, bordered eq. 8 system by sparse LU.  The GPU result comes
+from six velocity Helmholtz solves and FGMRES on the pressure matrix, so its error is the
+FGMRES tolerance times the conditioning of C (plus the velocity solves' own error); the
+bars below are derived that way: FGMRES to 1e-12 with FP64 solves gives errors near 1e-11
+on these grids, and the refined split-BF16 velocity solves (1e-11 each) cap the reachable
+FGMRES residual near 1e-11, so those run to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import solvers, stokes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1107_2461_amd import load
+    load()
+    return t
+
+
+def _faces(n, betas=(1.5, 1.0, 2.0)):
+    return tuple(workloads.stretched_faces(n[d], betas[d]) for d in range(3))
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("precision,method,tol,bar", [("fp64", "tpt", 1e-12, 1e-9), ("fp64", "tpf", 1e-12, 1e-9),
+                                                      ("bf16x3_ir", "tpf", 1e-10, 1e-7)])
+@pytest.mark.parametrize("n,tau,with_g", [((13, 9, 11), 1e2, False), ((12, 10, 14), 1e-1, True)])
+def test_stokes_matches_assembled_oracle(torch, precision, method, tol, bar, n, tau, with_g):
+    from paper_1107_2461_amd import PressureMatrix
+    faces = _faces(n)
+    orc = stokes.StokesSystem(faces, 1.0 / tau)
+    rng = np.random.default_rng(21)
+    f = [rng.uniform(-1, 1, orc.shapes[d]) for d in range(3)]
+    g = rng.uniform(-1, 1, (n[2], n[1], n[0])) if with_g else None   # keeps its mean: dropped by both
+    ux, uy, uz, p, c = orc.solve(f, g)
+    pm = PressureMatrix(faces, tau, precision=precision, method=method)
+    assert pm.velocity_shapes() == tuple(orc.shapes)
+    out = pm.stokes([torch.from_numpy(x).cuda() for x in f], None if g is None else torch.from_numpy(g).cuda(),
+                    tol=tol, max_it=400, restart=40, precondition=2)
+    info = pm.last_info
+    assert info["converged"], info
+    got = [t.cpu().numpy() for t in out]
+    for d, ref in enumerate((ux, uy, uz)):
+        assert _rel(got[d], ref) <= bar, (d, _rel(got[d], ref))
+    assert _rel(got[3], p) <= bar
+    assert abs(solvers.weighted_mean(got[3].ravel(), orc.vol)) <= 1e-12 * np.abs(p).max()
+    # the rows of eq. 8 on the GPU result
+    mom, div = orc.apply(got[:3], got[3])
+    scale = max(np.abs(x).max() for x in f)
+    for d in range(3):
+        assert np.abs(mom[d] - f[d]).max() <= 10 * bar * scale
+    gt = np.zeros_like(div) if g is None else g - solvers.weighted_mean(g.ravel(), orc.vol)
+    assert np.abs(div - gt).max() <= 10 * bar * max(scale, np.abs(gt).max())
+
+
+def test_stokes_pure_gradient_forcing(torch):
+    """f = Grad q, g = 0: the pressure alone balances the forcing (u = 0, p = q - mean)."""
+    from paper_1107_2461_amd import PressureMatrix
+    n = (10, 12, 9)
+    faces = _faces(n)
+    orc = stokes.StokesSystem(faces, 1.0)
+    q = np.random.default_rng(22).uniform(-1, 1, orc.np)
+    f = [(orc.G[d] @ q).reshape(orc.shapes[d]) for d in range(3)]
+    pm = PressureMatrix(faces, 1.0)
+    out = pm.stokes([torch.from_numpy(x).cuda() for x in f], tol=1e-12, max_it=200, restart=30)
+    assert pm.last_info["converged"], pm.last_info
+    scale = max(np.abs(x).max() for x in f)
+    for d in range(3):
+        assert np.abs(out[d].cpu().numpy()).max() <= 1e-9 * scale
+    q0 = solvers.project(q, orc.vol)
+    assert _rel(out[3].cpu().numpy().ravel(), q0) <= 1e-9
+
+
+def test_stokes_rejects_aliasing_and_shapes(torch):
+    import ctypes as C
+    from paper_1107_2461_amd import PressureMatrix, _lib, load
+    n = (6, 5, 7)
+    pm = PressureMatrix(_faces(n), 1.0)
+    shapes = pm.velocity_shapes()
+    f = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in shapes]
+    with pytest.raises(ValueError):
+        pm.stokes([f[1], f[0], f[2]])
+    lib = load()
+    nb = C.c_size_t()
+    assert lib.helm_stokes_workspace_size(pm._h, 30, C.byref(nb)) == _lib.HELM_OK
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    wsp = C.c_void_p((ws.data_ptr() + 255) // 256 * 256)
+    p = torch.empty((n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
+    fa = (C.c_void_p * 3)(*[x.data_ptr() for x in f])
+    info = _lib.HelmInfo()
+    # u aliasing f is refused before any launch
+    st = lib.helm_stokes_solve(pm._h, fa, None, fa, C.c_void_p(p.data_ptr()), 1e-10, 10, 30, 2, wsp, None,
+                               C.byref(info))
+    assert st == _lib.HELM_EINVAL
+    assert lib.helm_stokes_workspace_size(pm._h, 0, C.byref(nb)) == _lib.HELM_EINVAL
