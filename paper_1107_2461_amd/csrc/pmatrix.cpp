@@ -298,23 +298,34 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
       } else {
         if ((e = scale(zj, vj, 1.0, np, st)) != hipSuccess) return st_from(e);
       }
-      if ((s = pm_apply(pm, zj, w, ws, L, st)) != HELM_OK) return s;
-      // classical Gram-Schmidt, twice
+      // w = C z_j is built in the basis slot j + 1, so that one multi-dot over V_0 .. V_{j+1}
+      // gives the projections and |w|^2 together
+      double* wv = V + (j + 1) * np;
+      if ((s = pm_apply(pm, zj, wv, ws, L, st)) != HELM_OK) return s;
+      // classical Gram-Schmidt with selective reorthogonalization (Daniel, Gragg, Kaufman &
+      // Stewart 1976): the norm after a pass follows from Pythagoras, |w'|^2 = |w|^2 - |h|^2;
+      // a second pass runs only when that cancels more than half of |w|^2 (eta = 1/sqrt 2),
+      // and an explicit norm only if the second pass cancels too
       std::fill(h.begin(), h.end(), 0.0);
-      for (int pass = 0; pass < 2; ++pass) {
-        if ((s = dots(pm, V, j + 1, w, ws, L, st, h2.data())) != HELM_OK) return s;
+      double hn = -1.0;
+      for (int pass = 0; pass < 2 && hn < 0.0; ++pass) {
+        if ((s = dots(pm, V, j + 2, wv, ws, L, st, h2.data())) != HELM_OK) return s;
+        const double ww = h2[j + 1];
+        double hh = 0.0;
         std::vector<double> c(j + 1);
         for (int i = 0; i <= j; ++i) {
           h[i] += h2[i];
           c[i] = -h2[i];
+          hh += h2[i] * h2[i];
         }
-        if ((s = axpys(pm, w, V, j + 1, c.data(), ws, L, st)) != HELM_OK) return s;
+        if ((s = axpys(pm, wv, V, j + 1, c.data(), ws, L, st)) != HELM_OK) return s;
+        const double est = ww - hh;
+        if (est > 0.5 * ww) hn = std::sqrt(est);
       }
-      double hn = 0.0;
-      if ((s = norm2(pm, w, ws, L, st, &hn)) != HELM_OK) return s;
+      if (hn < 0.0 && (s = norm2(pm, wv, ws, L, st, &hn)) != HELM_OK) return s;
       h[j + 1] = hn;
-      if (hn > 0.0 && j + 1 <= m) {
-        if ((e = scale(V + (j + 1) * np, w, 1.0 / hn, np, st)) != hipSuccess) return st_from(e);
+      if (hn > 0.0) {
+        if ((e = scale(wv, wv, 1.0 / hn, np, st)) != hipSuccess) return st_from(e);
       }
       // apply previous rotations, then a new one to annihilate h[j+1]
       for (int i = 0; i < j; ++i) {
