@@ -713,24 +713,59 @@ hipError_t fill(double* y, long long n, double value, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Stage 1: block b of vector j sums a strided slice of V_j . w into partial[j][b].
+// Krylov-basis reductions and updates of FGMRES.  Both stream the basis once per call: a
+// thread reads its slice of w (or its outputs) once for up to kDotVec basis vectors, with
+// 16-byte loads when every row is 16-byte aligned (VW = 2) and 8-byte loads otherwise.
+constexpr int kDotVec = 16;
+template <int VW>
+struct DotVec;
+template <>
+struct DotVec<1> {
+  typedef double T;
+  __device__ static double dot(T a, T b) { return a * b; }
+};
+template <>
+struct DotVec<2> {
+  typedef double T __attribute__((ext_vector_type(2)));
+  __device__ static double dot(T a, T b) { return a.x * b.x + a.y * b.y; }
+};
+
+// Stage 1: block b sums its grid-strided slice of V_j . w for the NV vectors V_0 .. V_{NV-1}
+// of this launch into partial[j][b] (fixed order: deterministic).  NV is a template
+// parameter so that no load is guarded: a guarded load would end its own basic block and the
+// wait at the join would serialize the loads.
+template <int VW, int NV>
 __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, long long ldv,
                                                   const double* __restrict__ w, long long n,
                                                   double* __restrict__ partial) {
-  __shared__ double sh[256];
-  const int j = blockIdx.y;
-  const double* vj = V + j * ldv;
-  double s = 0.0;
-  for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < n;
-       i += static_cast<long long>(gridDim.x) * 256)
-    s += vj[i] * w[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
+  typedef typename DotVec<VW>::T T;
+  __shared__ double sh[4][NV];
+  const long long nq = n / VW;  // VW = 2 only when n is even
+  const T* wq = reinterpret_cast<const T*>(w);
+  double s[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) s[j] = 0.0;
+  for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < nq;
+       i += static_cast<long long>(gridDim.x) * 256) {
+    const T wv = wq[i];
+    T v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = reinterpret_cast<const T*>(V + j * ldv)[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s[j] += DotVec<VW>::dot(v[j], wv);
   }
-  if (threadIdx.x == 0) partial[static_cast<long long>(j) * gridDim.x + blockIdx.x] = sh[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double v = s[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) sh[wave][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV)
+    partial[static_cast<long long>(threadIdx.x) * gridDim.x + blockIdx.x] =
+        (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 // Stage 2: one block per vector sums its partials in a fixed tree order.
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int nblk,
@@ -748,28 +783,81 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
   if (threadIdx.x == 0) out[j] = sh[0];
 }
 
+namespace {
+bool rows16(const void* p, long long ldv, long long n) {
+  return reinterpret_cast<uintptr_t>(p) % 16 == 0 && ldv % 2 == 0 && n % 2 == 0;
+}
+}  // namespace
+
+namespace {
+template <int VW, int NV>
+void launch_multidot(const double* V, long long ldv, const double* w, long long n, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_multidot<VW, NV>), dim3(kDotBlocks), dim3(256), 0, st, V, ldv, w, n, partial);
+}
+// one launch for nv (1 .. kDotVec) vectors
+template <int VW>
+void multidot_chunk(int nv, const double* V, long long ldv, const double* w, long long n, double* partial,
+                    hipStream_t st) {
+  switch (nv) {
+#define HELM_DOT_CASE(k) \
+  case k: launch_multidot<VW, k>(V, ldv, w, n, partial, st); break;
+    HELM_DOT_CASE(1) HELM_DOT_CASE(2) HELM_DOT_CASE(3) HELM_DOT_CASE(4) HELM_DOT_CASE(5) HELM_DOT_CASE(6)
+    HELM_DOT_CASE(7) HELM_DOT_CASE(8) HELM_DOT_CASE(9) HELM_DOT_CASE(10) HELM_DOT_CASE(11) HELM_DOT_CASE(12)
+    HELM_DOT_CASE(13) HELM_DOT_CASE(14) HELM_DOT_CASE(15) HELM_DOT_CASE(16)
+#undef HELM_DOT_CASE
+    default: break;
+  }
+}
+}  // namespace
+
 hipError_t multi_dot(const double* V, long long ldv, int nvec, const double* w, long long n, double* partial,
                      double* out, hipStream_t st) {
   if (nvec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_multidot, dim3(kDotBlocks, nvec), dim3(256), 0, st, V, ldv, w, n, partial);
+  static_assert(kDotVec == 16, "multidot_chunk instantiates 1 .. 16 vectors");
+  const bool v2 = rows16(V, ldv, n) && reinterpret_cast<uintptr_t>(w) % 16 == 0;
+  for (int j0 = 0; j0 < nvec; j0 += kDotVec) {
+    const int nv = std::min(kDotVec, nvec - j0);
+    double* pj = partial + static_cast<long long>(j0) * kDotBlocks;
+    if (v2)
+      multidot_chunk<2>(nv, V + j0 * ldv, ldv, w, n, pj, st);
+    else
+      multidot_chunk<1>(nv, V + j0 * ldv, ldv, w, n, pj, st);
+  }
   hipLaunchKernelGGL(k_sum_partials, dim3(nvec), dim3(256), 0, st, partial, kDotBlocks, out);
   return hipGetLastError();
 }
 
+// w[i] += sum_j coef[j] V_j[i]: each thread owns VW consecutive points and reads its values of
+// every basis vector once (eight vectors per unrolled step).
+template <int VW>
 __global__ __launch_bounds__(256) void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V,
                                                     long long ldv, int nvec, const double* __restrict__ coef,
                                                     long long n) {
+  typedef typename DotVec<VW>::T T;
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = w[i];
-  for (int j = 0; j < nvec; ++j) s += coef[j] * V[j * ldv + i];
-  w[i] = s;
+  if (i >= n / VW) return;
+  T* wq = reinterpret_cast<T*>(w);
+  T s = wq[i];
+  int j = 0;
+  for (; j + 8 <= nvec; j += 8) {
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = reinterpret_cast<const T*>(V + (j + q) * ldv)[i];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += coef[j + q] * v[q];
+  }
+  for (; j < nvec; ++j) s += coef[j] * reinterpret_cast<const T*>(V + j * ldv)[i];
+  wq[i] = s;
 }
 hipError_t multi_axpy(double* w, const double* V, long long ldv, int nvec, const double* coef, long long n,
                       hipStream_t st) {
   if (n <= 0 || nvec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_multi_axpy, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, w, V, ldv, nvec,
-                     coef, n);
+  if (rows16(V, ldv, n) && reinterpret_cast<uintptr_t>(w) % 16 == 0)
+    hipLaunchKernelGGL(k_multi_axpy<2>, dim3(static_cast<unsigned>((n / 2 + 255) / 256)), dim3(256), 0, st, w, V,
+                       ldv, nvec, coef, n);
+  else
+    hipLaunchKernelGGL(k_multi_axpy<1>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, w, V, ldv,
+                       nvec, coef, n);
   return hipGetLastError();
 }
 
