@@ -242,6 +242,22 @@ def source_hash(prec):
     return h.hexdigest()[:16]
 
 
+def sustained_peak(prec, bound):
+    """The rate the probes sustain on this chip for a kernel's bound (profiles/peaks.json,
+    written from `bench.py --workload peaks`): the MFMA loop of its precision (a split-BF16
+    product issues six BF16 products per algorithmic one) or the HBM copy; None if absent."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "peaks.json")) as fh:
+            pk = json.load(fh)["peaks"]
+    except (OSError, ValueError, KeyError):
+        return None
+    if bound == "hbm":
+        return pk.get("hbm_copy", {}).get("gbps")
+    if prec == "bf16x3":
+        return pk["bf16"]["tflops"] / 6 if "bf16" in pk else None
+    return pk.get(prec, {}).get("tflops")
+
+
 def committed_traffic(prec, stage):
     """HBM bytes per launch of a stage from profiles/traffic.json, if taken on the current sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -338,6 +354,61 @@ def run_stokes(torch, prob, tau, precision, steps, method="tpt"):
         f"{res['ms_per_solve']:.1f} ms")
     del pm
     return res
+
+
+def run_peaks(torch):
+    """Sustained matrix rate per precision (MFMA-only probe loops, helm_probe_mfma) and HBM
+    rate (a 2 GiB device copy, far beyond the 256 MB last-level cache, helm_probe_copy),
+    each after a warm-up long enough for the clocks to settle; the datasheet peaks beside."""
+    import ctypes as C
+    from paper_1107_2461_amd import _lib, load
+    lib = load()
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    blocks = 1024                                  # two rounds of two workgroups per compute unit
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+
+    def timed(launch, reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            launch()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+
+    res = {}
+    for kind, name, steps, peak in ((0, "bf16", 16384, 2500.0), (1, "fp32", 4096, 157.3), (2, "fp64", 4096, 78.6)):
+        best = None
+        for chains in (4, 8, 16):                  # the best chain count differs between the forms
+            fl = C.c_double()
+            iters = steps // chains                # the same matrix work per launch at every count
+
+            def launch():
+                _lib.check(lib.helm_probe_mfma(kind, chains, iters, blocks, C.c_void_p(out.data_ptr()), sp,
+                                               C.byref(fl)), "helm_probe_mfma")
+            timed(launch, 60)                      # clocks settle
+            sec = timed(launch, 40)
+            tf = fl.value / sec / 1e12
+            log(f"[peaks] {name} x{chains}: {tf:.1f} TFLOP/s")
+            if best is None or tf > best["tflops"]:
+                best = dict(tflops=tf, chains=chains, datasheet_tflops=peak, frac=tf / peak, us_per_launch=sec * 1e6)
+        res[name] = best
+        log(f"[peaks] {name}: {best['tflops']:.1f} TFLOP/s ({best['frac']:.2f} of {peak})")
+    nbytes = 2 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+
+    def copy():
+        _lib.check(lib.helm_probe_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, sp),
+                   "helm_probe_copy")
+    timed(copy, 10)
+    sec = timed(copy, 20)
+    res["hbm_copy"] = dict(gbps=2 * nbytes / sec / 1e9, datasheet_gbps=8000.0, frac=2 * nbytes / sec / 8e12,
+                           us_per_launch=sec * 1e6, bytes_moved=2 * nbytes)
+    log(f"[peaks] HBM copy: {res['hbm_copy']['gbps']:.0f} GB/s ({res['hbm_copy']['frac']:.2f} of 8000)")
+    print(json.dumps(dict(metric="sustained peaks (probes)", n_gpus=1, data="synthetic", peaks=res)))
 
 
 def run_pressure(torch, args):
@@ -677,7 +748,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="mixed_256",
-                    help="mixed_256 (default), multirhs_128, small_32, pressure, serving")
+                    help="mixed_256 (default), multirhs_128, small_32, pressure, serving, peaks")
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -711,6 +782,9 @@ def main():
     if args.workload == "pressure":
         run_pressure(torch, args)
         return
+    if args.workload == "peaks":
+        run_peaks(torch)
+        return
     prob, f, gname, extra = build_workload(args.workload)
     golden = None
     if gname:
@@ -742,6 +816,9 @@ def main():
     roofline = dict(kernel=dom, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
                     frac=d["frac"], traffic=committed_traffic(b["precision"], dom), avg_us=d["avg_us"],
                     algorithmic_bytes=d.get("algorithmic_bytes"), algorithmic_flops=d.get("algorithmic_flops"))
+    sp = sustained_peak(b["precision"], d["bound"])
+    if sp:
+        roofline.update(sustained_peak=sp, frac_of_sustained=d["achieved"] / sp)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

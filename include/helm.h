@@ -230,6 +230,20 @@ helm_status helm_profile_read(helm_plan* plan, double* ms, int* launches);
  * Returns EINVAL for a null plan or a mask with no valid stage bit. */
 helm_status helm_profile_stages(helm_plan* plan, unsigned stage_mask);
 
+/* Measurement probes (no solve uses them): the rates the chip sustains on this software stack,
+ * beside the datasheet peaks the kernel rooflines are quoted against.
+ * helm_probe_mfma launches `blocks` workgroups of four waves, each wave running `iters` steps of
+ * `chains` (4, 8 or 16) independent MFMA chains on register operands: kind 0 = BF16 16x16x32
+ * with FP32 accumulation, 1 = FP32 16x16x4, 2 = FP64 16x16x4.  out: device buffer of
+ * blocks * 256 floats (written, to keep the chains live).  *flops (host, nullable) receives
+ * the matrix flops of the launch.  Asynchronous on `stream`; EINVAL for a bad kind or chain
+ * count, iters or blocks < 1, or null out.
+ * helm_probe_copy copies `bytes` (a multiple of 16) between two 16-byte aligned, non-overlapping
+ * device buffers with 16-byte loads and stores on `stream`; EINVAL otherwise. */
+helm_status helm_probe_mfma(int kind, int chains, int iters, int blocks, float* out, void* stream,
+                            double* flops);
+helm_status helm_probe_copy(const void* src, void* dst, long long bytes, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of solve requests on one GPU.
  *

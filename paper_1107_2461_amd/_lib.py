@@ -79,6 +79,8 @@ SIGNATURES = {
     "helm_profile_enable": (C.c_int, [P, C.c_int]),
     "helm_profile_read": (C.c_int, [P, DP, IP]),
     "helm_profile_stages": (C.c_int, [P, C.c_uint]),
+    "helm_probe_mfma": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, P, P, DP]),
+    "helm_probe_copy": (C.c_int, [P, P, C.c_longlong, P]),
     "helm_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_double, C.POINTER(HelmOpts), C.POINTER(P)]),
     "helm_server_submit": (C.c_int, [P, C.POINTER(HelmGrid), C.POINTER(HelmBC), DP, C.c_int, P, P, C.c_longlong]),
     "helm_server_poll": (C.c_int, [P, C.POINTER(HelmRequestRecord), C.c_int, IP, C.c_int]),
