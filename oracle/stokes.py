@@ -29,9 +29,12 @@ from . import fv
 
 
 class StokesSystem:
-    """Assembled, bordered Stokes matrix of eq. 8 for a pressure grid and shift sigma_v."""
+    """Assembled, bordered Stokes matrix of eq. 8 for a pressure grid and shift sigma_v.
 
-    def __init__(self, faces, sigma_v):
+    factorize=False keeps only the blocks (for apply() at sizes where the sparse LU of the
+    bordered matrix would be too large)."""
+
+    def __init__(self, faces, sigma_v, factorize=True):
         self.faces = tuple(np.asarray(f, dtype=np.float64) for f in faces)
         self.sigma_v = float(sigma_v)
         self.n = tuple(len(f) - 1 for f in self.faces)          # pressure cells (nx, ny, nz)
@@ -55,6 +58,9 @@ class StokesSystem:
             Z[3][d] = self.D[d]
         Z[3][3] = sp.csr_matrix((self.np, self.np))
         self.S = sp.bmat(Z, format="csr")                         # eq. 8 in the library's signs
+        self._lu = None
+        if not factorize:
+            return
         nt = self.S.shape[0]
         ones_p = np.zeros(nt)
         ones_p[nt - self.np:] = 1.0                               # constant in the continuity rows

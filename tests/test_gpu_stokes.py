@@ -105,3 +105,31 @@ def test_stokes_rejects_aliasing_and_shapes(torch):
                                C.byref(info))
     assert st == _lib.HELM_EINVAL
     assert lib.helm_stokes_workspace_size(pm._h, 0, C.byref(nb)) == _lib.HELM_EINVAL
+
+
+@pytest.mark.parametrize("precision,method,rel", [("fp64", "tpt", 1e-12), ("bf16x3_ir", "tpf", 1e-9)])
+def test_stokes_rows_multi_tile(torch, precision, method, rel):
+    """At a size spanning several 16-wide MFMA blocks with ragged tails (pressure 40 x 37 x 45),
+    the rows of eq. 8 on the GPU result with the oracle's sparse blocks: the momentum rows as a
+    backward error (the velocity solves' accuracy times the size of the terms), the continuity
+    rows to the FGMRES tolerance times the size of the divergence terms."""
+    from paper_1107_2461_amd import PressureMatrix
+    n = (40, 37, 45)
+    faces = _faces(n)
+    tau, tol = 10.0, 1e-10
+    orc = stokes.StokesSystem(faces, 1.0 / tau, factorize=False)
+    rng = np.random.default_rng(23)
+    f = [rng.uniform(-1, 1, orc.shapes[d]) for d in range(3)]
+    pm = PressureMatrix(faces, tau, precision=precision, method=method)
+    out = pm.stokes([torch.from_numpy(x).cuda() for x in f], tol=tol, max_it=400, restart=40, precondition=2)
+    assert pm.last_info["converged"], pm.last_info
+    got = [t.cpu().numpy() for t in out]
+    mom, div = orc.apply(got[:3], got[3])
+    pmax = np.abs(got[3]).max()
+    for d in range(3):
+        hn = abs(orc.H[d]).sum(axis=1).max()
+        gn = abs(orc.G[d]).sum(axis=1).max()
+        size = hn * np.abs(got[d]).max() + gn * pmax + np.abs(f[d]).max()
+        assert np.abs(mom[d] - f[d]).max() <= rel * size, (d, np.abs(mom[d] - f[d]).max() / size)
+    dsize = max(abs(orc.D[d]).sum(axis=1).max() * np.abs(got[d]).max() for d in range(3))
+    assert np.abs(div).max() <= 10 * tol * dsize, np.abs(div).max() / dsize
