@@ -827,6 +827,80 @@ hipError_t multi_dot(const double* V, long long ldv, int nvec, const double* w, 
   return hipGetLastError();
 }
 
+// w[i] += sum_j coef[j] V_j[i] for the NV vectors of the basis, then the projections V_j . w and
+// |w|^2 of the updated w, in one sweep: each thread keeps its values of the NV vectors in
+// registers between the update and the products (two points per thread, 16-byte loads).
+// partial[j][b] for j < NV, partial[NV][b] = |w|^2 (fixed order: deterministic).
+template <int NV>
+__global__ __launch_bounds__(256) void k_axpy_dot(double* __restrict__ w, const double* __restrict__ V,
+                                                  long long ldv, const double* __restrict__ coef, long long n,
+                                                  double* __restrict__ partial) {
+  typedef DotVec<2>::T T;
+  __shared__ double sh[4][NV + 1];
+  const long long nq = n / 2;
+  T* wq = reinterpret_cast<T*>(w);
+  double c[NV], s[NV + 1];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) c[j] = coef[j];
+#pragma unroll
+  for (int j = 0; j <= NV; ++j) s[j] = 0.0;
+  for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < nq;
+       i += static_cast<long long>(gridDim.x) * 256) {
+    T v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = reinterpret_cast<const T*>(V + j * ldv)[i];
+    T x = wq[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x += c[j] * v[j];
+    wq[i] = x;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s[j] += DotVec<2>::dot(v[j], x);
+    s[NV] += DotVec<2>::dot(x, x);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j <= NV; ++j) {
+    double v = s[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) sh[wave][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x <= NV)
+    partial[static_cast<long long>(threadIdx.x) * gridDim.x + blockIdx.x] =
+        (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+
+namespace {
+template <int NV>
+void launch_axpy_dot(double* w, const double* V, long long ldv, const double* coef, long long n, double* partial,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_dot<NV>), dim3(kDotBlocks), dim3(256), 0, st, w, V, ldv, coef, n, partial);
+}
+template <int NV>
+bool axpy_dot_upto(int nvec, double* w, const double* V, long long ldv, const double* coef, long long n,
+                   double* partial, hipStream_t st) {
+  if constexpr (NV > kAxpyDotMax) {
+    return false;
+  } else {
+    if (nvec == NV) {
+      launch_axpy_dot<NV>(w, V, ldv, coef, n, partial, st);
+      return true;
+    }
+    return axpy_dot_upto<NV + 1>(nvec, w, V, ldv, coef, n, partial, st);
+  }
+}
+}  // namespace
+
+hipError_t multi_axpy_dot(double* w, const double* V, long long ldv, int nvec, const double* coef, long long n,
+                          double* partial, double* out, hipStream_t st) {
+  if (nvec < 1 || nvec > kAxpyDotMax || !rows16(V, ldv, n) || reinterpret_cast<uintptr_t>(w) % 16)
+    return hipErrorInvalidValue;
+  if (!axpy_dot_upto<1>(nvec, w, V, ldv, coef, n, partial, st)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sum_partials, dim3(nvec + 1), dim3(256), 0, st, partial, kDotBlocks, out);
+  return hipGetLastError();
+}
+
 // w[i] += sum_j coef[j] V_j[i]: each thread owns VW consecutive points and reads its values of
 // every basis vector once (eight vectors per unrolled step).
 template <int VW>

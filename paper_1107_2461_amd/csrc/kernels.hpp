@@ -140,6 +140,13 @@ hipError_t fill(double* y, long long n, double value, hipStream_t st);
 constexpr int kDotBlocks = 256;
 hipError_t multi_dot(const double* V, long long ldv, int nvec, const double* w, long long n, double* partial,
                      double* out, hipStream_t st);
+// One sweep of w[i] += sum_j coef[j] * V[j * ldv + i] followed by out[j] = V_j . w (j < nvec)
+// and out[nvec] = |w|^2 of the updated w; nvec <= kAxpyDotMax, rows and w 16-byte aligned,
+// ldv and n even (else hipErrorInvalidValue, nothing launched).  partial: (nvec + 1) *
+// kDotBlocks doubles of device scratch; out: nvec + 1 doubles (device).
+constexpr int kAxpyDotMax = 32;
+hipError_t multi_axpy_dot(double* w, const double* V, long long ldv, int nvec, const double* coef, long long n,
+                          double* partial, double* out, hipStream_t st);
 // w[i] += sum_j coef[j] * V[j * ldv + i]   (coef: device array of nvec values)
 hipError_t multi_axpy(double* w, const double* V, long long ldv, int nvec, const double* coef, long long n,
                       hipStream_t st);

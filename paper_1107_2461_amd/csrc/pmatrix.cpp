@@ -147,6 +147,26 @@ helm_status axpys(helm_pmat* pm, double* w, const double* V, int k, const double
   return st_from(e);
 }
 
+// w += sum_j c[j] V_j (c on the host), then host <- V_j . w (j < k) and |w|^2 of the updated w,
+// in one sweep; false (nothing done) when the fused kernel does not apply (k or alignment)
+bool axpy_dots(helm_pmat* pm, double* w, const double* V, int k, const double* c, unsigned char* ws,
+               const PmLayout& L, hipStream_t st, double* out, helm_status* s) {
+  double* coef = reinterpret_cast<double*>(ws + L.coef);
+  double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* dd = reinterpret_cast<double*>(ws + L.dots);
+  if (k > kAxpyDotMax || pm->np % 2 || reinterpret_cast<uintptr_t>(V) % 16 || reinterpret_cast<uintptr_t>(w) % 16)
+    return false;
+  std::memcpy(pm->host, c, k * sizeof(double));
+  hipError_t e = hipMemcpyAsync(coef, pm->host, k * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = multi_axpy_dot(w, V, pm->np, k, coef, pm->np, partial, dd, st);
+  // the download reuses the pinned buffer after the upload (same stream, in order)
+  if (e == hipSuccess) e = hipMemcpyAsync(pm->host, dd, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = helm::wait_stream(st);
+  *s = st_from(e);
+  if (e == hipSuccess) std::memcpy(out, pm->host, (k + 1) * sizeof(double));
+  return true;
+}
+
 helm_status norm2(helm_pmat* pm, const double* x, unsigned char* ws, const PmLayout& L, hipStream_t st,
                   double* out) {
   double v = 0.0;
@@ -308,7 +328,45 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
       // and an explicit norm only if the second pass cancels too
       std::fill(h.begin(), h.end(), 0.0);
       double hn = -1.0;
-      for (int pass = 0; pass < 2 && hn < 0.0; ++pass) {
+      // With the fused sweep, the first pass's update and the second pass's projections (and
+      // the exact |w'|^2) share one sweep over V; the second update runs only if needed.
+      bool fused = false;
+      {
+        if ((s = dots(pm, V, j + 2, wv, ws, L, st, h2.data())) != HELM_OK) return s;
+        const double ww = h2[j + 1];
+        std::vector<double> c(j + 1), d2(j + 2);
+        for (int i = 0; i <= j; ++i) {
+          h[i] = h2[i];
+          c[i] = -h2[i];
+        }
+        helm_status sf = HELM_OK;
+        fused = axpy_dots(pm, wv, V, j + 1, c.data(), ws, L, st, d2.data(), &sf);
+        if (sf != HELM_OK) return sf;
+        if (fused) {
+          const double ww2 = d2[j + 1];
+          if (ww2 > 0.5 * ww) {
+            hn = std::sqrt(ww2);  // little cancellation: the remaining projections are dropped
+          } else {
+            double hh = 0.0;
+            for (int i = 0; i <= j; ++i) {
+              h[i] += d2[i];
+              c[i] = -d2[i];
+              hh += d2[i] * d2[i];
+            }
+            if ((s = axpys(pm, wv, V, j + 1, c.data(), ws, L, st)) != HELM_OK) return s;
+            const double est = ww2 - hh;
+            if (est > 0.5 * ww2) hn = std::sqrt(est);
+          }
+        } else {
+          // separate passes: finish the first one here
+          double hh = 0.0;
+          for (int i = 0; i <= j; ++i) hh += h2[i] * h2[i];
+          if ((s = axpys(pm, wv, V, j + 1, c.data(), ws, L, st)) != HELM_OK) return s;
+          const double est = ww - hh;
+          if (est > 0.5 * ww) hn = std::sqrt(est);
+        }
+      }
+      for (int pass = 1; pass < 2 && hn < 0.0 && !fused; ++pass) {
         if ((s = dots(pm, V, j + 2, wv, ws, L, st, h2.data())) != HELM_OK) return s;
         const double ww = h2[j + 1];
         double hh = 0.0;
