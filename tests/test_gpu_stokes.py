@@ -133,3 +133,58 @@ def test_stokes_rows_multi_tile(torch, precision, method, rel):
         assert np.abs(mom[d] - f[d]).max() <= rel * size, (d, np.abs(mom[d] - f[d]).max() / size)
     dsize = max(abs(orc.D[d]).sum(axis=1).max() * np.abs(got[d]).max() for d in range(3))
     assert np.abs(div).max() <= 10 * tol * dsize, np.abs(div).max() / dsize
+
+
+def test_stokes_minimum_grid(torch):
+    """Three pressure cells per axis (two velocity nodes along each velocity's own axis)."""
+    from paper_1107_2461_amd import PressureMatrix
+    n = (3, 3, 3)
+    faces = _faces(n)
+    orc = stokes.StokesSystem(faces, 0.5)
+    rng = np.random.default_rng(24)
+    f = [rng.uniform(-1, 1, orc.shapes[d]) for d in range(3)]
+    ux, uy, uz, p, _ = orc.solve(f)
+    pm = PressureMatrix(faces, 2.0)
+    # unpreconditioned: the velocity solves at two and three unknowns per axis are the paths
+    # exercised here (the shortest-axis and Thomas-length tests cover them on their own)
+    out = pm.stokes([torch.from_numpy(x).cuda() for x in f], tol=1e-13, max_it=100, restart=20, precondition=0)
+    assert pm.last_info["converged"], pm.last_info
+    for d, ref in enumerate((ux, uy, uz)):
+        assert _rel(out[d].cpu().numpy(), ref) <= 1e-10
+    assert _rel(out[3].cpu().numpy(), p) <= 1e-10
+
+
+def test_stokes_not_converged_reports_and_returns_finite(torch):
+    """max_it = 1: the status says so, and u, p come from the best pressure found (finite;
+    the velocities still satisfy the momentum rows for that pressure)."""
+    import ctypes as C
+    from paper_1107_2461_amd import PressureMatrix, _lib, load
+    n = (12, 10, 14)
+    faces = _faces(n)
+    orc = stokes.StokesSystem(faces, 0.01, factorize=False)
+    rng = np.random.default_rng(25)
+    f = [rng.uniform(-1, 1, orc.shapes[d]) for d in range(3)]
+    pm = PressureMatrix(faces, 100.0)
+    ft = [torch.from_numpy(x).cuda() for x in f]
+    out = pm.stokes(ft, tol=1e-14, max_it=1, restart=5, precondition=0)
+    assert not pm.last_info["converged"] and pm.last_info["iterations"] == 1
+    got = [t.cpu().numpy() for t in out]
+    assert all(np.isfinite(g).all() for g in got)
+    mom, _ = orc.apply(got[:3], got[3])
+    for d in range(3):
+        size = (abs(orc.H[d]).sum(axis=1).max() * np.abs(got[d]).max()
+                + abs(orc.G[d]).sum(axis=1).max() * np.abs(got[3]).max() + np.abs(f[d]).max())
+        assert np.abs(mom[d] - f[d]).max() <= 1e-12 * size
+    # the C ABI reports the same through its status
+    lib = load()
+    nb = C.c_size_t()
+    assert lib.helm_stokes_workspace_size(pm._h, 5, C.byref(nb)) == _lib.HELM_OK
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    u = [torch.empty_like(x) for x in ft]
+    p = torch.empty((n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
+    info = _lib.HelmInfo()
+    st = lib.helm_stokes_solve(pm._h, (C.c_void_p * 3)(*[x.data_ptr() for x in ft]), None,
+                               (C.c_void_p * 3)(*[x.data_ptr() for x in u]), C.c_void_p(p.data_ptr()), 1e-14, 1, 5,
+                               0, C.c_void_p((ws.data_ptr() + 255) // 256 * 256), None, C.byref(info))
+    torch.cuda.synchronize()
+    assert st == _lib.HELM_ENOTCONVERGED and info.converged == 0 and info.iterations == 1
