@@ -411,6 +411,76 @@ def run_peaks(torch):
     print(json.dumps(dict(metric="sustained peaks (probes)", n_gpus=1, data="synthetic", peaks=res)))
 
 
+def run_timestep(torch, args):
+    """The solver work of one step of the paper's time integration (Section 5.1, eqs. 37-40) on
+    its largest 3D grid, 100^3 cells (beta = 1.5): one temperature Helmholtz solve (cell
+    centred; Dirichlet on the two heated x walls, Neumann on the others), three velocity
+    Helmholtz solves (each on its staggered grid, no-slip walls) and one pressure Poisson solve
+    (all-Neumann), with Pr = 0.71, Gr = 1e7, dt = 1e-3: sigma_T = 3 Pr Gr^1/2 / (2 dt) and
+    sigma_v = 3 Gr^1/2 / (2 dt) from the second-order backward time derivative.  Right-hand
+    sides are seeded N(0, 1) (the pressure one made mean-free); the advective terms, which are
+    not solver work, are not computed.  value = time steps per second."""
+    from paper_1107_2461_amd import CELL, DIRICHLET, FACE, NEUMANN, Plan
+    n, beta, pr, gr, dt = 100, 1.5, 0.71, 1e7, 1e-3
+    faces = tuple(workloads.stretched_faces(n, beta) for _ in range(3))
+    sig_t, sig_v = 3 * pr * gr ** 0.5 / (2 * dt), 3 * gr ** 0.5 / (2 * dt)
+    rng = np.random.default_rng(6)
+    paths = {}
+    for path, prec, method in (("fp64_tpt", "fp64", "tpt"), ("fp64_tpf", "fp64", "tpf"),
+                               ("bf16x3_ir", "bf16x3_ir", "tpf")):
+        plans = [("T", Plan(faces, bc_lo=(DIRICHLET, NEUMANN, NEUMANN), bc_hi=(DIRICHLET, NEUMANN, NEUMANN),
+                            sigma=sig_t, precision=prec, method=method))]
+        for d, name in enumerate(("u", "v", "w")):
+            loc = [CELL] * 3
+            loc[d] = FACE
+            plans.append((name, Plan(faces, sigma=sig_v, loc=tuple(loc), precision=prec, method=method)))
+        plans.append(("p", Plan(faces, pressure=True, precision=prec, method=method)))
+        fs, us = [], []
+        for name, pl in plans:
+            shp = (1,) + tuple(reversed(pl.shape_xyz))
+            f = rng.standard_normal(shp)
+            if name == "p":
+                f = workloads.remove_weighted_mean(f, faces)
+            fs.append(torch.from_numpy(f).cuda())
+            us.append(torch.empty(shp, dtype=torch.float64, device="cuda"))
+
+        def step():
+            for (name, pl), f, u in zip(plans, fs, us):
+                pl.solve(f, out=u)
+        for _ in range(max(3, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res = {}
+        for (name, pl), f, u in zip(plans, fs, us):
+            r = f - pl.apply(u)
+            res[name] = float(r.norm() / f.norm())
+        pts = sum(int(np.prod(pl.shape_xyz)) for _, pl in plans)
+        ms = 1e3 * float(np.median(ts))
+        paths[path] = dict(ms_per_step=ms, steps_per_s=1e3 / ms, solves_per_step=len(plans), points_per_step=pts,
+                           rel_residuals=res)
+        log(f"[bench] time step {path}: {ms:.3f} ms ({1e3 / ms:.0f} steps/s), residuals "
+            + " ".join(f"{k} {v:.1e}" for k, v in res.items()))
+        del plans
+    best = min(paths, key=lambda k: paths[k]["ms_per_step"])
+    b = paths[best]
+    line = dict(metric="time steps/s (temperature, three velocity and one pressure solve, eqs. 37-40)",
+                value=b["steps_per_s"], unit="steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=b["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64" if best.startswith("fp64") else "bf16x3", data="synthetic",
+                config=dict(workload="timestep_100cube_gr1e7", grid=[n, n, n], stretch=beta, pr=pr, gr=gr, dt=dt,
+                            path=best),
+                paper_context_ms_per_step=dict(tpt=1259.89e3 / 1e4, tpf=1842.8e3 / 1e4,
+                                               note="Table 3, 100^3, Gr = 1e7, one vector CPU core"),
+                paths=paths)
+    print(json.dumps(line))
+
+
 def run_pressure(torch, args):
     """The pressure workload: all-Neumann pressure Laplacian solves (eq. 28) and FGMRES on the
     pressure matrix C (eq. 9) with tau = 100."""
@@ -748,7 +818,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="mixed_256",
-                    help="mixed_256 (default), multirhs_128, small_32, pressure, serving, peaks")
+                    help="mixed_256 (default), multirhs_128, small_32, pressure, serving, peaks, timestep")
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -784,6 +854,9 @@ def main():
         return
     if args.workload == "peaks":
         run_peaks(torch)
+        return
+    if args.workload == "timestep":
+        run_timestep(torch, args)
         return
     prob, f, gname, extra = build_workload(args.workload)
     golden = None
