@@ -90,6 +90,34 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
                 algorithmic_bytes=byts)
 
 
+def sweep_errors(torch, prob, f_dev, golden, nrhs):
+    """Error against the oracle samples (max over the samples, relative to max|u|) after each
+    refinement sweep, from solves with that fixed sweep count (ir_tol = 0), for the refined
+    precisions; and of the unrefined low-precision solves.  Untimed."""
+    from paper_1107_2461_amd import Plan
+
+    def err(u):
+        uh = u.cpu().numpy().reshape(nrhs, -1)
+        return max(float(np.abs(uh[r, np.array(g["idx"])] - np.array(g["u"])).max() / g["norminf"])
+                   for r, g in enumerate(golden["rhs"][:nrhs]))
+    out = {}
+    for prec, smax in (("bf16x3_ir", 3), ("fp32_ir", 3), ("bf16_ir", 9)):
+        errs = []
+        for sweeps in range(1, smax + 1):
+            pl = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, loc=prob.loc, precision=prec, ir_tol=0.0,
+                      max_sweeps=sweeps)
+            errs.append(err(pl.solve(f_dev)))
+            del pl
+        out[prec] = errs
+        log(f"[bench] {prec} error after 1..{smax} sweeps: " + " ".join(f"{e:.1e}" for e in errs))
+    for prec in ("bf16x3", "fp32", "bf16"):
+        pl = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, loc=prob.loc, precision=prec)
+        out[prec] = err(pl.solve(f_dev))
+        del pl
+        log(f"[bench] unrefined {prec}: error {out[prec]:.1e}")
+    return out
+
+
 def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     from paper_1107_2461_amd import Plan
     prec = {"fp64": "fp64", "fp32_ir": "fp32_ir", "bf16_ir": "bf16_ir", "bf16x3_ir": "bf16x3_ir", "tpt": "fp64"}[path]
@@ -906,6 +934,7 @@ def main():
     sp = sustained_peak(b["precision"], d["bound"])
     if sp:
         roofline.update(sustained_peak=sp, frac_of_sustained=d["achieved"] / sp)
+    swe = sweep_errors(torch, prob, f_dev, golden, nrhs) if golden is not None else None
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -916,7 +945,7 @@ def main():
                 else "f64", data="synthetic",
                 config=dict(workload=prob.name, grid=list(prob.shape_xyz), stretch=1.5, nrhs=nrhs,
                             sigma=prob.sigma, path=best, **extra),
-                p50_ms=b["p50_ms"], p99_ms=b["p99_ms"], roofline=roofline, cpu_baseline=cpu,
+                p50_ms=b["p50_ms"], p99_ms=b["p99_ms"], roofline=roofline, cpu_baseline=cpu, sweep_errors=swe,
                 paths={k: {kk: vv for kk, vv in v.items()} for k, v in results.items()})
     print(json.dumps(line))
 
