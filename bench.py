@@ -323,9 +323,10 @@ def run_pressure_matrix(torch, prob, f, tau, precision, steps, method="tpf", pcs
             ts.append(time.perf_counter() - t0)
         info = pm.last_info
         r = float((b - pm.apply(p)).norm() / b.norm())
-        out[name] = dict(iterations=info["iterations"], converged=bool(info["converged"]), rel_residual=r,
-                         ms_per_solve=1e3 * float(np.median(ts)))
-        log(f"[bench] FGMRES {method} precond={name}: {info['iterations']} it, res {r:.2e}, "
+        out[name] = dict(iterations=info["iterations"], helmholtz_solves=info["helmholtz_solves"],
+                         converged=bool(info["converged"]), rel_residual=r, ms_per_solve=1e3 * float(np.median(ts)))
+        log(f"[bench] FGMRES {method} precond={name}: {info['iterations']} it, {info['helmholtz_solves']} solves, "
+            f"res {r:.2e}, "
             f"{out[name]['ms_per_solve']:.1f} ms")
     del pm
     return out
@@ -375,7 +376,8 @@ def run_stokes(torch, prob, tau, precision, steps, method="tpt"):
         ts.append(time.perf_counter() - t0)
     info = pm.last_info
     mom, div = stokes_rows(torch, prob.faces, tau, out[:3], out[3], f)
-    res = dict(precision=precision, method=method, iterations=info["iterations"], converged=bool(info["converged"]),
+    res = dict(precision=precision, method=method, iterations=info["iterations"],
+               helmholtz_solves=info["helmholtz_solves"], converged=bool(info["converged"]),
                fgmres_rel_residual=info["residual"], momentum_rel_residual=mom, continuity_rel_residual=div,
                ms_per_solve=1e3 * float(np.median(ts)))
     log(f"[bench] Stokes {precision}/{method}: {info['iterations']} it, rows {mom:.1e} / {div:.1e}, "

@@ -176,7 +176,9 @@ helm_status helm_pmatrix_apply(helm_pmat* pm, const double* p, double* y, void* 
  * the pressure Laplacian (Cahouet & Chabard's form: it equals option 1 as tau -> 0 and the
  * identity as tau -> infinity).  b must have zero volume-weighted mean; p is returned with
  * zero volume-weighted mean.  Stops when the relative residual ||b - C p|| / ||b|| <= tol
- * (confirmed with a true residual) or after max_it iterations (ENOTCONVERGED).
+ * (confirmed with a true residual) or after max_it iterations (ENOTCONVERGED).  info (host,
+ * nullable): iterations, the final relative residual, converged, and in `sweeps` the number of
+ * Helmholtz solves performed (three per action of C, one per preconditioner application).
  * Synchronizes a few times per iteration (Gram-Schmidt coefficients). */
 helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double* p, double tol, int max_it,
                                int restart, int use_precond, void* ws, void* stream,
@@ -203,7 +205,8 @@ helm_status helm_stokes_workspace_size(const helm_pmat* pm, int restart, size_t*
  *   ws: helm_stokes_workspace_size bytes, 256-byte aligned, owned by the caller.
  * Costs six velocity solves plus the FGMRES iterations (three velocity solves each).
  * Returns the first failing velocity solve's status, else helm_pmatrix_solve's (u is then
- * computed from the best p); info gets the FGMRES iterations and relative residual. */
+ * computed from the best p); info gets the FGMRES iterations and relative residual, and in
+ * `sweeps` all Helmholtz solves (the six of steps 1 and 3 plus those of the FGMRES). */
 helm_status helm_stokes_solve(helm_pmat* pm, const double* const f[3], const double* g,
                               double* const u[3], double* p, double tol, int max_it, int restart,
                               int use_precond, void* ws, void* stream, helm_info* info);

@@ -279,7 +279,8 @@ class PressureMatrix:
         st = load().helm_pmatrix_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(p.data_ptr()), float(tol),
                                        int(max_it), int(restart), int(precondition),
                                        self._workspace(restart, b.device), _stream_ptr(stream), C.byref(info))
-        self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK)
+        self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK,
+                              helmholtz_solves=info.sweeps)
         if st not in (_lib.HELM_OK, _lib.HELM_ENOTCONVERGED):
             check(st, "helm_pmatrix_solve")
         return p
@@ -318,7 +319,8 @@ class PressureMatrix:
         st = lib.helm_stokes_solve(self._h, fa, C.c_void_p(g.data_ptr() if g is not None else None), ua,
                                    C.c_void_p(p.data_ptr()), float(tol), int(max_it), int(restart), int(precondition),
                                    Plan._aligned(ws), _stream_ptr(stream), C.byref(info))
-        self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK)
+        self.last_info = dict(iterations=info.iterations, residual=info.residual, converged=st == _lib.HELM_OK,
+                              helmholtz_solves=info.sweeps)
         if st not in (_lib.HELM_OK, _lib.HELM_ENOTCONVERGED):
             check(st, "helm_stokes_solve")
         return u[0], u[1], u[2], p

@@ -279,6 +279,7 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
   }
   if (bnorm == 0.0) return HELM_OK;
   int it = 0;
+  int nsolves = 0;  // Helmholtz solves: three per action of C, one per preconditioner application
   double relres = 1.0;
   std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), gvec(m + 1), h(m + 1), h2(m + 1);
   bool first = true;
@@ -288,6 +289,7 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
       e = scale(r, b, 1.0, np, st);
     } else {
       if ((s = pm_apply(pm, p, w, ws, L, st)) != HELM_OK) return s;
+      nsolves += 3;
       e = scale(r, b, 1.0, np, st);
       if (e == hipSuccess) {
         const double minus1 = -1.0;
@@ -311,6 +313,7 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
       if (use_precond == 1 || use_precond == 2) {
         helm_info pi;
         s = helm_pressure_solve(pm->pres, vj, zj, 1, ws + L.presws, st, &pi);
+        ++nsolves;
         if (s != HELM_OK && s != HELM_ENOTCONVERGED) return s;
         if (use_precond == 2) {  // z = v + sigma_v * A_p^{-1} v
           if ((e = axpby(zj, 1.0 / pm->tau, vj, 1.0, np, st)) != hipSuccess) return st_from(e);
@@ -322,6 +325,7 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
       // gives the projections and |w|^2 together
       double* wv = V + (j + 1) * np;
       if ((s = pm_apply(pm, zj, wv, ws, L, st)) != HELM_OK) return s;
+      nsolves += 3;
       // classical Gram-Schmidt with selective reorthogonalization (Daniel, Gragg, Kaufman &
       // Stewart 1976): the norm after a pass follows from Pythagoras, |w'|^2 = |w|^2 - |h|^2;
       // a second pass runs only when that cancels more than half of |w|^2 (eta = 1/sqrt 2),
@@ -417,6 +421,7 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
     if (relres <= tol) {
       // confirm with the true residual
       if ((s = pm_apply(pm, p, w, ws, L, st)) != HELM_OK) return s;
+      nsolves += 3;
       if ((e = scale(r, b, 1.0, np, st)) != hipSuccess) return st_from(e);
       const double minus1 = -1.0;
       if ((s = axpys(pm, r, w, 1, &minus1, ws, L, st)) != HELM_OK) return s;
@@ -430,6 +435,7 @@ extern "C" helm_status helm_pmatrix_solve(helm_pmat* pm, const double* b, double
     info->iterations = it;
     info->residual = relres;
     info->converged = relres <= tol;
+    info->sweeps = nsolves;
   }
   return relres <= tol ? HELM_OK : HELM_ENOTCONVERGED;
 }
@@ -512,7 +518,7 @@ extern "C" helm_status helm_stokes_solve(helm_pmat* pm, const double* const f[3]
     info->iterations = ci.iterations;
     info->residual = ci.residual;
     info->converged = ci.converged;
-    info->sweeps = 0;
+    info->sweeps = 6 + ci.sweeps;
     info->last_correction = 0.0;
   }
   return sc;

@@ -168,6 +168,8 @@ def test_stokes_not_converged_reports_and_returns_finite(torch):
     ft = [torch.from_numpy(x).cuda() for x in f]
     out = pm.stokes(ft, tol=1e-14, max_it=1, restart=5, precondition=0)
     assert not pm.last_info["converged"] and pm.last_info["iterations"] == 1
+    # six velocity solves of steps 1 and 3, three for the one action of C (no preconditioner)
+    assert pm.last_info["helmholtz_solves"] == 9
     got = [t.cpu().numpy() for t in out]
     assert all(np.isfinite(g).all() for g in got)
     mom, _ = orc.apply(got[:3], got[3])
@@ -187,4 +189,4 @@ def test_stokes_not_converged_reports_and_returns_finite(torch):
                                (C.c_void_p * 3)(*[x.data_ptr() for x in u]), C.c_void_p(p.data_ptr()), 1e-14, 1, 5,
                                0, C.c_void_p((ws.data_ptr() + 255) // 256 * 256), None, C.byref(info))
     torch.cuda.synchronize()
-    assert st == _lib.HELM_ENOTCONVERGED and info.converged == 0 and info.iterations == 1
+    assert st == _lib.HELM_ENOTCONVERGED and info.converged == 0 and info.iterations == 1 and info.sweeps == 9
