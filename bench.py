@@ -736,6 +736,10 @@ PROFILE_COMMANDS = (
 PROFILE_TRACE_128 = ("rocprofv3 --kernel-trace --stats --output-format csv -d {d}/kt128 -o kt -- "
                      "python -u bench.py --workload multirhs_128 --steps 5 --warmup 1 --no-cpu-baseline "
                      "--paths fp64,tpt,bf16x3_ir")
+# kernel durations of the pressure workload: pressure solves, FGMRES on C with both
+# preconditioners and TPF / TPT velocity solves, and the Stokes solve (192 x 160 x 224 cells)
+PROFILE_TRACE_PRESSURE = ("rocprofv3 --kernel-trace --stats --output-format csv -d {d}/ktp -o kt -- "
+                          "python -u bench.py --workload pressure --steps 1 --warmup 1")
 # HBM traffic of the Thomas pass (TPT, 128^3 x 3 RHS), one counter per run, with the same copy
 # calibration as the 256^3 runs.
 PROFILE_TRAFFIC_128 = tuple(
@@ -789,6 +793,9 @@ def summarize_profiles(d, copy_mb=1024, npts=256 ** 3, workload="256^3 Helmholtz
     kernel_table("kt", f"{workload}, all arithmetic paths", cmds[0], "kernel_stats_helmholtz_256cube.md")
     kernel_table("kt128", "128^3 x 3 RHS (tau = 1e-3, 1, 1e2): FP64 TPF, TPT (Thomas in z), split-BF16",
                  PROFILE_TRACE_128.format(d=d), "kernel_stats_helmholtz_128cube_x3.md")
+    kernel_table("ktp", "pressure workload, 192 x 160 x 224 cells: pressure solves, FGMRES on the pressure "
+                 "matrix (eq. 9, tau = 100) and the Stokes solve (eq. 8)", PROFILE_TRACE_PRESSURE.format(d=d),
+                 "kernel_stats_pressure_stokes_192x160x224.md")
     # HBM traffic: per-dispatch counters, calibrated on the copy of copy_mb MiB
     per = {}
     scale = {}
