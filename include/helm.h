@@ -163,6 +163,9 @@ helm_status helm_pressure_solve(helm_plan* plan, const double* f, double* p, int
  * the pressure Laplacian (the Chorin limit of C, end of Section 2).  Errors as helm_setup. */
 helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, const helm_opts* opts,
                                helm_pmat** out);
+/* A helm_pmat holds one pinned host buffer for its Krylov scalars: calls on one helm_pmat
+ * (apply, solve, Stokes solve) must not overlap; distinct helm_pmat objects may be used
+ * concurrently. */
 
 /* Workspace bytes for helm_pmatrix_apply / helm_pmatrix_solve with restart length m. */
 helm_status helm_pmatrix_workspace_size(const helm_pmat* pm, int restart, size_t* bytes);
