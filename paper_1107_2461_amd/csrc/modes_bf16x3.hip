@@ -38,6 +38,21 @@ hipError_t launch_rot(const bf16_t* Mp, long long piece, int KB, int K, const vo
   return hipGetLastError();
 }
 
+// Halves the tile height (row blocks per wave) while a launch would not fill one round of the
+// chip (256 CUs x 2 resident workgroups), down to one 16-row block per wave: small grids and
+// slabs get enough workgroups, large ones keep the tile that reads M once per 128 rows.
+template <int CI, int RW>
+hipError_t launch_fit(const bf16_t* Mp, long long piece, int KB, int K, const void* Xv, bool x_f64, void* Y,
+                      long long R, long long PQ, Epi epi, bool vec, const EpiArgs& ep, hipStream_t st) {
+  if constexpr (RW > 1) {
+    constexpr Cfg c = kCfgs[CI];
+    constexpr int MT = (4 / c.W) * RW * 16;
+    if ((R * PQ + MT - 1) / MT < 512)
+      return launch_fit<CI, RW / 2>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
+  }
+  return launch_rot<CI, RW>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
+}
+
 }  // namespace
 
 hipError_t mode_rot_bf16x3(int ci, const void* Msw, long long piece, int K, const void* Xv, bool x_f64, void* Y,
@@ -47,14 +62,8 @@ hipError_t mode_rot_bf16x3(int ci, const void* Msw, long long piece, int K, cons
   return for_cfg(ci, [&](auto cic) -> hipError_t {
     constexpr int CI = decltype(cic)::value;
     constexpr Cfg c = kCfgs[CI];
-    constexpr int RW = rot_rows(c);  // row blocks per wave
-    constexpr int MT = (4 / c.W) * RW * 16;
-    // Half-height tiles when the full ones would not fill one round of the chip (256 CUs x 2
-    // resident workgroups): small grids get twice the workgroups, large ones keep the tile
-    // that reads M once per 128 rows.
-    if (RW > 1 && (R * PQ + MT - 1) / MT < 512)
-      return launch_rot<CI, (RW > 1 ? RW / 2 : 1)>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
-    return launch_rot<CI, RW>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
+    constexpr int RW = rot_rows(c);  // row blocks per wave of the full tile
+    return launch_fit<CI, RW>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
   });
 }
 
