@@ -61,6 +61,19 @@ def test_longest_axis_512(torch, axis):
     assert _err(_run(torch, prob, f, precision="bf16x3_ir"), ref) <= 1e-10
 
 
+@pytest.mark.parametrize("n", [(256, 6, 5), (5, 6, 256), (7, 256, 3)])
+def test_long_axis_few_rows_split_bf16(torch, n):
+    # a 256-long axis with few rows to transform: the split-BF16 launcher shrinks its tiles to
+    # 16 rows so the launch still spreads over the chip (one GPU's slab in a sharded solve)
+    faces = tuple(workloads.stretched_faces(n[d], 1.5) for d in range(3))
+    prob = workloads.Problem(faces=faces, bc_lo=(D, N, D), bc_hi=(D, D, N), sigma=0.2)
+    f = workloads.rhs_uniform(71, 3, prob.shape_xyz)
+    sig = [0.2, 5.0, 0.01]
+    ref = _oracle(prob, f, sig)
+    assert _err(_run(torch, prob, f, sigma=sig, precision="bf16x3_ir"), ref) <= 1e-10
+    assert _err(_run(torch, prob, f, sigma=sig, precision="bf16x3"), ref) <= 1e-5
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3_ir", 1e-10), ("fp32_ir", 1e-10)])
 def test_shortest_axes(torch, precision, tol):
     # two cells per axis, and a face-located axis with two interior unknowns (n = 3)
