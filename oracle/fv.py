@@ -9,7 +9,9 @@ reading used throughout is written out here, Section 3 eq. 23 and Section 5.1):
   value 0 at distance c_0 - x_0 (resp. x_n - c_{n-1}); at a Neumann wall it is 0.
 * Face-located unknowns (a staggered velocity in its own direction): nodes at the
   interior faces x_1..x_{n-1}, control volume [c_{i-1}, c_i]; a Dirichlet wall
-  value 0 sits on the wall face, at distance x_1 - x_0 (resp. x_n - x_{n-1}).
+  value 0 sits on the wall face, at distance x_1 - x_0 (resp. x_n - x_{n-1}); at a
+  Neumann wall the outer end of the first (last) control volume, the cell centre
+  c_0 (c_{n-1}), carries no flux.
 * The FV Laplacian is (1/vol) * sum over the control volume's faces of
   area * flux; the library solves (sigma I - Laplacian_h) u = f.
 

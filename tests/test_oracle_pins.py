@@ -38,6 +38,8 @@ def test_operator_1d_hand_fixture():
         "cell_neumann": (fv.CELL, N, N),
         "cell_dirichlet_lo_neumann_hi": (fv.CELL, D, N),
         "face_dirichlet": (fv.FACE, D, D),
+        "face_neumann": (fv.FACE, N, N),
+        "face_dirichlet_lo_neumann_hi": (fv.FACE, D, N),
     }
     for key, (loc, lo, hi) in cases.items():
         K, vol = fv.operator_1d(faces, loc, lo, hi)
@@ -82,6 +84,37 @@ def test_uniform_eigs_closed_form_face():
         v = np.sin(np.pi * a * i / n)
         lam = 4 / h**2 * np.sin(np.pi * a / (2 * n)) ** 2
         np.testing.assert_allclose(A @ v, lam * v, atol=1e-10 * 4 / h**2)
+
+
+@pytest.mark.parametrize("bc", ["NN", "DN", "ND"])
+def test_uniform_eigs_closed_form_face_neumann(bc):
+    """Face-located nodes with a Neumann wall: on a uniform grid the m = n - 1 nodes have
+    control volumes h and link conductances 1/h, a Dirichlet wall adds 1/h (wall value at
+    distance h) and a Neumann wall nothing, so A = (1/h^2) tridiag(-1, 2, -1) with the end
+    diagonals 1 (Neumann) -- the DCT-II matrix for NN, a DST-VII-type one for DN/ND."""
+    n, L = 13, 0.9
+    h = L / n
+    m = n - 1
+    lo = D if bc[0] == "D" else N
+    hi = D if bc[1] == "D" else N
+    K, vol = fv.operator_1d(_uniform_faces(n, L), fv.FACE, lo, hi)
+    np.testing.assert_allclose(vol, np.full(m, h), rtol=1e-13)
+    A = K / vol[:, None]
+    i = np.arange(m)
+    lam = []
+    for a in range(m):
+        if bc == "NN":
+            v = np.cos(np.pi * a * (i + 0.5) / m)
+            la = 4 / h**2 * np.sin(np.pi * a / (2 * m)) ** 2
+        elif bc == "DN":
+            v = np.sin(np.pi * (2 * a + 1) * (i + 1) / (2 * m + 1))
+            la = 4 / h**2 * np.sin(np.pi * (2 * a + 1) / (2 * (2 * m + 1))) ** 2
+        else:
+            v = np.sin(np.pi * (2 * a + 1) * (m - i) / (2 * m + 1))
+            la = 4 / h**2 * np.sin(np.pi * (2 * a + 1) / (2 * (2 * m + 1))) ** 2
+        np.testing.assert_allclose(A @ v, la * v, rtol=0, atol=1e-10 * 4 / h**2)
+        lam.append(la)
+    np.testing.assert_allclose(np.sort(np.linalg.eigvals(A).real), np.sort(lam), rtol=1e-12, atol=1e-9)
 
 
 # ------------------------------------------------------------------ 3D assembly
@@ -207,6 +240,34 @@ def test_uniform_face_located_matches_dst1():
     g = sfft.idst(g, type=2, axis=0, norm="ortho")
     g = sfft.idst(g, type=2, axis=1, norm="ortho")
     ref = sfft.idst(g, type=1, axis=2, norm="ortho")
+    assert solvers.rel_err(u[0], ref) < 1e-13
+
+
+def test_uniform_face_located_neumann_matches_dct2():
+    """x face-located with Neumann walls (DCT-II of length n - 1), y cell-centred Dirichlet
+    (DST-II), z cell-centred Dirichlet-Neumann (DST-IV), against scipy.fft transforms."""
+    n = (9, 6, 7)
+    L = (1.0, 1.0, 2.0)
+    faces = tuple(_uniform_faces(n[d], L[d]) for d in range(3))
+    h = [L[d] / n[d] for d in range(3)]
+    loc = fv.velocity_loc(0)
+    sigma = 0.7
+    rng = np.random.default_rng(13)
+    f = rng.uniform(-1, 1, (n[2], n[1], n[0] - 1))
+    u, _ = solvers.solve_problem(faces, sigma, f[None], loc=loc, bc_lo=(N, D, D), bc_hi=(N, D, N),
+                                 method="dense")
+    g = sfft.dct(f, type=2, axis=2, norm="ortho")
+    g = sfft.dst(g, type=2, axis=1, norm="ortho")
+    g = sfft.dst(g, type=4, axis=0, norm="ortho")
+    m = n[0] - 1
+    ex = 4 / h[0]**2 * np.sin(np.pi * np.arange(m) / (2 * m)) ** 2
+    ey = 4 / h[1]**2 * np.sin(np.pi * (np.arange(n[1]) + 1) / (2 * n[1])) ** 2
+    ez = 4 / h[2]**2 * np.sin(np.pi * (2 * np.arange(n[2]) + 1) / (4 * n[2])) ** 2
+    lam = ex[None, None, :] + ey[None, :, None] + ez[:, None, None]
+    g = g / (lam + sigma)
+    g = sfft.idst(g, type=4, axis=0, norm="ortho")
+    g = sfft.idst(g, type=2, axis=1, norm="ortho")
+    ref = sfft.idct(g, type=2, axis=2, norm="ortho")
     assert solvers.rel_err(u[0], ref) < 1e-13
 
 
