@@ -125,3 +125,31 @@ def test_refused_bounds(torch):
     plan = Plan(faces, sigma=1.0)
     with pytest.raises(HelmError, match="EINVAL"):
         plan.solve(torch.zeros((65, 4, 5, 6), dtype=torch.float64, device="cuda"))   # more than 64 RHS
+
+
+@pytest.mark.parametrize("precision,method,tol", [("fp64", "tpf", 1e-12), ("fp64", "tpt", 1e-12),
+                                                  ("bf16x3_ir", "tpf", 1e-10)])
+def test_face_located_neumann_axes(torch, precision, method, tol):
+    # face-located unknowns next to a Neumann wall (the oracle's reading, pinned by the hand
+    # fixture and the uniform-grid DCT-II closed form): x face-located with Neumann at both
+    # ends, z face-located with Dirichlet below and Neumann above (the Thomas axis)
+    n = (21, 18, 23)
+    faces = tuple(workloads.stretched_faces(n[d], 1.5) for d in range(3))
+    prob = workloads.Problem(faces=faces, bc_lo=(N, D, D), bc_hi=(N, D, N), loc=(fv.FACE, fv.CELL, fv.FACE),
+                             sigma=0.8)
+    f = workloads.rhs_uniform(81, 2, prob.shape_xyz)
+    sig = [0.8, 25.0]
+    ref = _oracle(prob, f, sig)
+    assert _err(_run(torch, prob, f, sigma=sig, precision=precision, method=method), ref) <= tol
+
+
+@pytest.mark.parametrize("n,nrhs", [((256, 16, 16), 64), ((256, 32, 16), 64)])
+def test_split_bf16_taller_tiles_few_rows(torch, n, nrhs):
+    # a 256-long x axis with 16384 (resp. 32768) rows in all: the split-BF16 x products run with
+    # tiles of 32 (resp. 64) rows per workgroup, the largest height that still gives 512
+    # workgroups; every right-hand side against the oracle
+    faces = tuple(workloads.stretched_faces(n[d], 1.5) for d in range(3))
+    prob = workloads.Problem(faces=faces, bc_lo=(D, N, D), bc_hi=(D, D, N), sigma=0.2)
+    f = workloads.rhs_uniform(72 + n[1], nrhs, prob.shape_xyz)
+    ref, _ = solvers.solve_problem(prob.faces, prob.sigma, f, prob.loc, prob.bc_lo, prob.bc_hi, method="splu")
+    assert _err(_run(torch, prob, f, precision="bf16x3_ir"), ref) <= 1e-10

@@ -1,10 +1,15 @@
 """Full-size GPU checks on the benchmark workloads, in the launch configuration bench.py times.
 
-The oracle cannot solve these sizes inside a test, so each comparison uses the oracle's
-solution at 2048 seeded grid points per RHS stored by tests/golden/make_oracle_samples.py
-(which calls only oracle/): err = max over samples |u - u_oracle| / max|u_oracle|.  Where a
-property holds at any size it is checked on the whole field as well (FP64 residual,
-TPF = TPT, zero mean of Neumann solutions).
+Three kinds of comparison with the CPU oracle:
+  * sampled forward error: the oracle's solution at 2048 seeded grid points per RHS stored by
+    tests/golden/make_oracle_samples.py (which calls only oracle/): max over samples
+    |u - u_oracle| / max|u_oracle|;
+  * whole-field backward error with the oracle's own operator (assembled cell by cell from face
+    fluxes, oracle.fv): ||f - H_oracle u||_2 / ||f||_2 per RHS, over every grid point;
+  * whole-field forward error in the 2-norm, ||u - u_oracle||_2 / ||u_oracle||_2, against a full
+    oracle solve (Jacobi-PCG to a true relative residual ~1e-14) for one 128^3 right-hand side.
+Properties that hold at any size are checked on the whole field as well (TPF = TPT, zero mean
+of Neumann solutions).
 """
 import json
 import os
@@ -13,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads
-from oracle import fv
+from oracle import fv, solvers
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -45,6 +50,31 @@ def _sample_err(u, g):
     return max(errs)
 
 
+_H_CACHE = {}
+
+
+def _oracle_matrix(prob):
+    """The oracle's assembled H = sigma I + diag(1/vol) K3 (cached per workload within the module)."""
+    key = prob.name
+    if key not in _H_CACHE:
+        _H_CACHE.clear()
+        H, K3, vol, _ = fv.helmholtz_matrix(prob.faces, prob.sigma, prob.loc, prob.bc_lo, prob.bc_hi)
+        _H_CACHE[key] = (H, vol)
+    return _H_CACHE[key]
+
+
+def _backward_err(prob, f, u, neumann=False):
+    """max over RHS of ||f - H_oracle u||_2 / ||f||_2 (f projected for the all-Neumann Laplacian)."""
+    H, vol = _oracle_matrix(prob)
+    out = []
+    for r in range(f.shape[0]):
+        fr = f[r].ravel()
+        if neumann:
+            fr = solvers.project(fr, vol)
+        out.append(float(np.linalg.norm(fr - H @ u[r].ravel()) / np.linalg.norm(fr)))
+    return max(out)
+
+
 def _plan(prob, **kw):
     from paper_1107_2461_amd import Plan
     return Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, loc=prob.loc, **kw)
@@ -64,6 +94,26 @@ def test_multirhs_128_tpf_tpt_fp64(torch, tau):
     assert e_tpf <= 1e-12 and e_tpt <= 1e-12
     for r in range(3):   # TPF and TPT agree on the whole field (Section 5.1)
         assert np.linalg.norm(a[r] - b[r]) / np.linalg.norm(a[r]) <= 1e-12
+    # every grid point: backward error with the oracle's assembled operator
+    be_tpf, be_tpt = _backward_err(prob, f, a), _backward_err(prob, f, b)
+    print(f"tau {tau}: backward error with the oracle operator TPF {be_tpf:.2e} TPT {be_tpt:.2e}")
+    assert be_tpf <= 1e-12 and be_tpt <= 1e-12
+
+
+def test_multirhs_128_full_oracle_solve_2norm(torch):
+    """One 128^3 right-hand side (tau = 1) against a full oracle PCG solve, over every point."""
+    prob, f = workloads.workload_multirhs_128(1.0)
+    f1 = f[:1].copy()
+    ref, info = solvers.solve_problem(prob.faces, prob.sigma, f1, method="pcg")
+    print("oracle PCG:", info)
+    fd = torch.from_numpy(f1).cuda()
+    for kw, tol in ((dict(), 1e-12), (dict(method="tpt"), 1e-12), (dict(precision="bf16x3_ir"), 1e-10),
+                    (dict(precision="fp32_ir"), 1e-10)):
+        u = _plan(prob, **kw).solve(fd)
+        torch.cuda.synchronize()
+        err = solvers.rel_err(u.cpu().numpy(), ref)
+        print(kw, f"||u - u_oracle||_2 / ||u_oracle||_2 = {err:.2e}")
+        assert err <= tol, (kw, err)
 
 
 def test_mixed_256_paths(torch):
@@ -79,10 +129,12 @@ def test_mixed_256_paths(torch):
         err = _sample_err(u.cpu().numpy(), g)
         out[precision] = (err, plan.last_info["sweeps"])
         assert err <= tol, (precision, err)
-        if precision == "fp64":
-            r = (fd - plan.apply(u)).norm() / fd.norm()
-            assert float(r) <= 1e-13
-    print("256^3 errors vs oracle samples (err, sweeps):", out)
+        if precision in ("fp64", "fp32_ir", "bf16_ir", "bf16x3_ir"):
+            # whole field: backward error with the oracle's assembled operator
+            be = _backward_err(prob, f, u.cpu().numpy())
+            out[precision] += (be,)
+            assert be <= (1e-12 if precision == "fp64" else 1e-10), (precision, be)
+    print("256^3 errors vs oracle samples (err, sweeps[, backward error]):", out)
 
 
 def test_mixed_256_error_per_sweep(torch):
@@ -122,6 +174,10 @@ def test_pressure_192x160x224_mixed(torch):
         assert err <= tol
         _, vol = fv.assemble_3d(prob.faces, bc_lo=(1,) * 3, bc_hi=(1,) * 3)[:2]
         assert abs((un.ravel() * vol).sum() / vol.sum()) <= 1e-12 * np.abs(un).max()
+        # whole field: -L_h p = P f with the oracle's assembled operator
+        be = _backward_err(prob, f, un, neumann=True)
+        print(precision, "pressure backward error with the oracle operator", be)
+        assert be <= (1e-12 if precision == "fp64" else 1e-10)
 
 
 def test_pressure_matrix_fgmres_full_size(torch):
