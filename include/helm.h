@@ -75,6 +75,17 @@ typedef struct {
   int hi[3];                /* ... at the high wall */
 } helm_bc;
 
+/* Device allocator callback (optional), so that a caller's allocator (e.g. PyTorch's caching
+ * allocator) owns the library's device memory.  alloc returns `bytes` bytes of device memory
+ * on the current HIP device, at least 256-byte aligned, or NULL on failure (reported as
+ * HELM_ENOMEM); dealloc releases a block returned by alloc, with the same size.  Both are
+ * called with the device current and may be called from the server's worker threads; they
+ * must stay valid until every object created with them is destroyed.  Blocks freed by
+ * dealloc may still be read by device work enqueued before the owning object's destroy
+ * call: the library synchronizes the device before releasing them. */
+typedef void* (*helm_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*helm_free_fn)(void* ptr, size_t bytes, void* ctx);
+
 typedef struct {
   int precision;            /* HELM_FP64 (default) ... HELM_BF16X3_IR */
   int method;               /* HELM_TPF (default) or HELM_TPT_Z */
@@ -85,6 +96,13 @@ typedef struct {
                                back, for callers that know their sweep count (see helm_solve) */
   int max_sweeps;           /* refinement sweep limit, including the first solve (default 12) */
   int null_mode;            /* HELM_NULL_PROJECT (default) or HELM_NULL_PAPER_EQ28 */
+  helm_alloc_fn alloc;      /* device allocator for everything the object allocates on the device
+                               (plan uploads, pressure-matrix vectors, the server's workspace
+                               arena); NULL (default) = hipMalloc / hipFree.  alloc and dealloc
+                               are both set or both NULL (else EINVAL).  Plans share their
+                               per-axis eigenbases only with plans of the same allocator. */
+  helm_free_fn dealloc;
+  void* alloc_ctx;          /* passed to alloc and dealloc */
 } helm_opts;
 
 typedef struct {
@@ -254,13 +272,16 @@ helm_status helm_probe_copy(const void* src, void* dst, long long bytes, void* s
  * Serving: continuous batching of solve requests on one GPU.
  *
  * Requests (grid, walls, per-RHS shifts, 1..64 right-hand sides, caller-owned device f and u)
- * are queued on submit.  A scheduler thread admits queued requests in arrival order while
- * (a) a solve slot is free and (b) the sum of the device workspace of the admitted requests
- * stays within the HBM budget; a request that does not fit waits until running requests
- * retire (a later, smaller request may pass it only if the head has waited less than
- * `max_bypass_ms`).  Each slot owns a HIP stream and a host worker thread, so admitted
- * solves run concurrently on the device and new requests are admitted while others are in
- * flight.  Plans (1D eigenbases) are cached on the device by their axis definition and
+ * are queued on submit.  Admission runs inside helm_server_submit and again whenever a slot
+ * finishes a request: queued requests are admitted in arrival order while (a) a solve slot is
+ * free and (b) the request's device workspace fits in a free range of the server's workspace
+ * arena, which is the whole HBM budget allocated once at creation (through opts->alloc when
+ * set); a request that does not fit waits until running requests retire (a later, smaller
+ * request may pass it only if the head has waited less than `max_bypass_ms`).  The server
+ * therefore holds exactly the budget in workspace memory and allocates nothing on the device
+ * while requests are in flight.  Each slot owns a HIP stream and a host worker thread, so
+ * admitted solves run concurrently on the device and new requests are admitted while others
+ * are in flight.  Plans (1D eigenbases) are cached on the device by their axis definition and
  * reused across requests.  When a request is admitted, queued requests on the same plan ride
  * along (up to 64 right-hand sides in all, within the budget, passing earlier requests only
  * under the same bypass rule): they are solved as one multi-RHS solve with each request's
@@ -285,15 +306,21 @@ typedef struct {
 } helm_request_record;
 
 /* Creates a server with `slots` concurrent solve slots (1..16) and a device-workspace budget
- * of hbm_budget_bytes; opts sets the arithmetic of every solve (NULL = FP64 TPF). */
+ * of hbm_budget_bytes (allocated at once as the workspace arena: ENOMEM if it cannot be had);
+ * opts sets the arithmetic of every solve and the allocator of the arena and of the resident
+ * plans (NULL = FP64 TPF, hipMalloc). */
 helm_status helm_server_create(size_t hbm_budget_bytes, int slots, double max_bypass_ms, const helm_opts* opts,
                                helm_server** out);
 /* Queues one request; returns at once.  f, u: device [nrhs][nz][ny][nx] float64 owned by the
  * caller, untouched until the request's record is returned by helm_server_poll.  sigma: host
- * array of nrhs shifts (copied).  Errors: EINVAL (bad arguments, or a footprint larger than
- * the whole budget, which could never be admitted). */
+ * array of nrhs shifts (copied).  stream: the caller's hipStream_t on which f is produced
+ * (NULL = the default stream); an event is recorded on it at submit and the solve waits for
+ * that event on the device, so work the caller enqueued before submitting completes before
+ * f is read.  u is complete when its record is polled (the slot's stream has finished).
+ * Errors: EINVAL (bad arguments, or a footprint larger than the whole budget, which could
+ * never be admitted), EDEVICE (the event could not be recorded). */
 helm_status helm_server_submit(helm_server* s, const helm_grid* grid, const helm_bc* bc, const double* sigma,
-                               int nrhs, const double* f, double* u, long long id);
+                               int nrhs, const double* f, double* u, long long id, void* stream);
 /* Returns up to max completed-request records (oldest first) in out and their count in *n,
  * waiting up to wait_ms milliseconds for at least one (0 = do not wait). */
 helm_status helm_server_poll(helm_server* s, helm_request_record* out, int max, int* n, int wait_ms);

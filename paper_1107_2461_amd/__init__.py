@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (BF16, BF16_IR, CELL, DIRICHLET, FACE, FP32, FP32_IR, FP64, NEUMANN, NULL_PAPER_EQ28,
                    NULL_PROJECT, TPF, TPT_Z, HelmError, check, load)
 
-__all__ = ["Plan", "PressureMatrix", "Server", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
+__all__ = ["Plan", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
            "NEUMANN", "CELL", "FACE", "FP64", "FP32", "BF16", "FP32_IR", "BF16_IR", "TPF", "TPT_Z",
            "NULL_PROJECT", "NULL_PAPER_EQ28"]
 
@@ -38,9 +38,63 @@ def _grid(faces, loc):
     return g, arrs
 
 
-def _opts(precision, method, ir_tol, max_sweeps, null_mode):
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator (helm_opts.alloc).
+
+    Each block the library asks for is a torch uint8 tensor kept here until the library
+    releases it, so torch.cuda.memory_allocated() counts the library's plans, pressure-matrix
+    vectors and server arenas.  The library synchronizes the device before it releases a
+    block, so the caching allocator may hand the memory out again at once.  Use the shared
+    instance from torch_allocator(): it must outlive every object built with it."""
+
+    def __init__(self):
+        import threading
+        self._blocks = {}
+        self._lock = threading.Lock()
+        self._fn_alloc = _lib.ALLOC_FN(self._alloc)
+        self._fn_free = _lib.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        torch = _torch()
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+        except RuntimeError:
+            return None
+        with self._lock:
+            self._blocks[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, nbytes, ctx):
+        with self._lock:
+            self._blocks.pop(ptr, None)
+
+    def blocks(self):
+        """Number of live blocks held for the library."""
+        with self._lock:
+            return len(self._blocks)
+
+    def fill(self, opts):
+        opts.alloc = self._fn_alloc
+        opts.dealloc = self._fn_free
+        opts.alloc_ctx = None
+
+
+_TORCH_ALLOCATOR = None
+
+
+def torch_allocator():
+    """The process-wide TorchAllocator (created on first use, never released)."""
+    global _TORCH_ALLOCATOR
+    if _TORCH_ALLOCATOR is None:
+        _TORCH_ALLOCATOR = TorchAllocator()
+    return _TORCH_ALLOCATOR
+
+
+def _opts(precision, method, ir_tol, max_sweeps, null_mode, allocator=None):
     o = _lib.HelmOpts()
     load().helm_default_opts(C.byref(o))
+    if allocator is not None:
+        allocator.fill(o)
     o.precision = _lib.PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
     o.method = _lib.METHODS.get(method, method) if isinstance(method, str) else int(method)
     if ir_tol is not None:
@@ -67,10 +121,10 @@ class Plan:
 
     def __init__(self, faces, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, sigma=0.0, loc=(CELL,) * 3,
                  precision="fp64", method="tpf", ir_tol=None, max_sweeps=None, null_mode=NULL_PROJECT,
-                 pressure=False):
+                 pressure=False, allocator=None):
         lib = load()
         g, self._faces = _grid(faces, loc)
-        opts = _opts(precision, method, ir_tol, max_sweeps, null_mode)
+        opts = _opts(precision, method, ir_tol, max_sweeps, null_mode, allocator)
         h = C.c_void_p()
         if pressure:
             check(lib.helm_pressure_setup(C.byref(g), C.byref(opts), C.byref(h)), "helm_pressure_setup")
@@ -230,14 +284,14 @@ def host_eigen_1d(faces, loc=CELL, bc_lo=DIRICHLET, bc_hi=DIRICHLET):
 class PressureMatrix:
     """Pressure matrix C of eq. 9 with FGMRES solve (helm_pmatrix_*)."""
 
-    def __init__(self, faces, tau, precision="fp64", method=None):
+    def __init__(self, faces, tau, precision="fp64", method=None, allocator=None):
         """method: "tpf" or "tpt" (FP64 only) for the velocity and pressure-preconditioner solves;
         None picks the Thomas variant in FP64 (the faster one there) and "tpf" otherwise."""
         lib = load()
         g, self._faces = _grid(faces, (CELL,) * 3)
         if method is None:
             method = "tpt" if precision == "fp64" else "tpf"
-        opts = _opts(precision, method, None, None, NULL_PROJECT)
+        opts = _opts(precision, method, None, None, NULL_PROJECT, allocator)
         h = C.c_void_p()
         check(lib.helm_pmatrix_setup(C.byref(g), float(tau), C.byref(opts), C.byref(h)), "helm_pmatrix_setup")
         self._h = h
@@ -329,17 +383,20 @@ class PressureMatrix:
 class Server:
     """Continuous-batching solve server (helm_server_*): submit requests, poll completions."""
 
-    def __init__(self, budget_bytes, slots=4, precision="fp64", max_bypass_ms=50.0, method="tpf"):
+    def __init__(self, budget_bytes, slots=4, precision="fp64", max_bypass_ms=50.0, method="tpf", allocator=None):
         lib = load()
-        opts = _opts(precision, method, None, None, NULL_PROJECT)
+        opts = _opts(precision, method, None, None, NULL_PROJECT, allocator)
         h = C.c_void_p()
         check(lib.helm_server_create(int(budget_bytes), int(slots), float(max_bypass_ms), C.byref(opts), C.byref(h)),
               "helm_server_create")
         self._h = h
         self._live = {}
 
-    def submit(self, rid, faces, f, u, sigma, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, loc=(CELL,) * 3):
-        """Queue one request; f, u: contiguous float64 CUDA tensors [nrhs, nz, ny, nx]; sigma: nrhs shifts."""
+    def submit(self, rid, faces, f, u, sigma, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, loc=(CELL,) * 3,
+               stream=None):
+        """Queue one request; f, u: contiguous float64 CUDA tensors [nrhs, nz, ny, nx]; sigma: nrhs shifts.
+        The solve waits on the device for the work enqueued on `stream` (torch's current stream
+        when None) before reading f."""
         g, arrs = _grid(faces, loc)
         bc = _lib.HelmBC()
         for d in range(3):
@@ -349,7 +406,8 @@ class Server:
         sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (nrhs,)))
         self._live[int(rid)] = (f, u)
         st = load().helm_server_submit(self._h, C.byref(g), C.byref(bc), sig.ctypes.data_as(_lib.DP), int(nrhs),
-                                       C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), int(rid))
+                                       C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), int(rid),
+                                       _stream_ptr(stream))
         if st != _lib.HELM_OK:
             self._live.pop(int(rid), None)
             check(st, "helm_server_submit")

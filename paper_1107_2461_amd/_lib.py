@@ -29,9 +29,14 @@ class HelmBC(C.Structure):
     _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3)]
 
 
+# helm_alloc_fn / helm_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
 class HelmOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("method", C.c_int), ("ir_tol", C.c_double), ("max_sweeps", C.c_int),
-                ("null_mode", C.c_int)]
+                ("null_mode", C.c_int), ("alloc", ALLOC_FN), ("dealloc", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class HelmInfo(C.Structure):
@@ -82,7 +87,8 @@ SIGNATURES = {
     "helm_probe_mfma": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, P, P, DP]),
     "helm_probe_copy": (C.c_int, [P, P, C.c_longlong, P]),
     "helm_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_double, C.POINTER(HelmOpts), C.POINTER(P)]),
-    "helm_server_submit": (C.c_int, [P, C.POINTER(HelmGrid), C.POINTER(HelmBC), DP, C.c_int, P, P, C.c_longlong]),
+    "helm_server_submit": (C.c_int, [P, C.POINTER(HelmGrid), C.POINTER(HelmBC), DP, C.c_int, P, P, C.c_longlong,
+                                     P]),
     "helm_server_poll": (C.c_int, [P, C.POINTER(HelmRequestRecord), C.c_int, IP, C.c_int]),
     "helm_server_drain": (C.c_int, [P]),
     "helm_server_now": (C.c_double, [P]),

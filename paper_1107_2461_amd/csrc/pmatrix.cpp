@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
+#include "alloc.hpp"
 #include "kernels.hpp"
 
 using namespace helm;
@@ -53,14 +54,17 @@ struct helm_pmat {
   double inv_volsum = 0.0;                          // 1 / (domain volume)
   double* host = nullptr;                           // pinned scratch (dots, coefficients)
   int device = 0;
+  DevAlloc alloc;                                   // allocator of inv_dc, inv_w, wid
   ~helm_pmat() {
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d)
       if (vel[d]) helm_destroy(vel[d]);
-      if (inv_dc[d]) (void)hipFree(inv_dc[d]);
-      if (inv_w[d]) (void)hipFree(inv_w[d]);
-      if (wid[d]) (void)hipFree(wid[d]);
+    if (pres) helm_destroy(pres);  // synchronizes the device: the vectors below are idle
+    for (int d = 0; d < 3; ++d) {
+      const size_t b = static_cast<size_t>(n[d]) * sizeof(double);
+      alloc.put(inv_dc[d], b);
+      alloc.put(inv_w[d], b);
+      alloc.put(wid[d], b);
     }
-    if (pres) helm_destroy(pres);
     if (host) (void)hipHostFree(host);
   }
 };
@@ -193,6 +197,8 @@ extern "C" helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, c
   helm_opts vo;
   helm_default_opts(&vo);
   if (opts) vo = *opts;
+  pm->alloc = DevAlloc::from(vo);
+  if (!pm->alloc.valid()) return HELM_EINVAL;
   if (vo.precision != HELM_FP64) vo.method = HELM_TPF;  // the Thomas variant runs in FP64 only
   for (int d = 0; d < 3; ++d) {
     helm_grid g = *p_grid;
@@ -222,9 +228,11 @@ extern "C" helm_status helm_pmatrix_setup(const helm_grid* p_grid, double tau, c
     }
     volsum *= len;
     for (int i = 0; i + 1 < n; ++i) idc[i] = 1.0 / (0.5 * (f[i + 2] - f[i]));  // c_{i+1} - c_i
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pm->inv_dc[d]), (n - 1) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pm->inv_w[d]), n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pm->wid[d]), n * sizeof(double));
+    // n doubles each (n - 1 used for inv_dc), so that each block is released with its size
+    const size_t nb = static_cast<size_t>(n) * sizeof(double);
+    hipError_t e = pm->alloc.get(reinterpret_cast<void**>(&pm->inv_dc[d]), nb);
+    if (e == hipSuccess) e = pm->alloc.get(reinterpret_cast<void**>(&pm->inv_w[d]), nb);
+    if (e == hipSuccess) e = pm->alloc.get(reinterpret_cast<void**>(&pm->wid[d]), nb);
     if (e == hipSuccess) e = hipMemcpy(pm->inv_dc[d], idc.data(), (n - 1) * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(pm->inv_w[d], iw.data(), n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(pm->wid[d], wd.data(), n * sizeof(double), hipMemcpyHostToDevice);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -24,6 +25,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
+#include "alloc.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -37,15 +39,65 @@ struct Pending {
 // Index (in the arrival-ordered queue) of the next request to admit, or -1.  The head is
 // admitted when it fits; otherwise a later request that fits may pass it only while the head
 // has waited less than max_bypass (after that, capacity is reserved for the head).
-template <typename Q>
-int pick_next(const Q& queue, int free_slots, size_t used, size_t budget, double now, double max_bypass) {
+// fits(foot): whether a workspace of `foot` bytes can be had now.
+template <typename Q, typename Fits>
+int pick_next(const Q& queue, int free_slots, Fits&& fits, double now, double max_bypass) {
   if (free_slots <= 0 || queue.empty()) return -1;
-  if (used + queue.front().foot <= budget) return 0;
+  if (fits(queue.front().foot)) return 0;
   if (now - queue.front().t_submit >= max_bypass) return -1;
   for (size_t i = 1; i < queue.size(); ++i)
-    if (used + queue[i].foot <= budget) return static_cast<int>(i);
+    if (fits(queue[i].foot)) return static_cast<int>(i);
   return -1;
 }
+
+// First-fit allocator of byte ranges (256-byte granules) inside the server's workspace arena:
+// the arena is the whole HBM budget, allocated once at creation, so the memory the server holds
+// is the budget itself and no device allocation happens while requests are in flight.
+class Arena {
+ public:
+  void reset(size_t bytes) {
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  // Largest contiguous free range.
+  size_t largest() const {
+    size_t m = 0;
+    for (auto& b : free_) m = std::max(m, b.second);
+    return m;
+  }
+  // Offset of a range of `bytes` (rounded up to 256), or SIZE_MAX if none is free.
+  size_t take(size_t bytes) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        return off;
+      }
+    return SIZE_MAX;
+  }
+  void give(size_t off, size_t bytes) {
+    bytes = round(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  static size_t round(size_t b) { return (b + 255) / 256 * 256; }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
+};
 
 // Plans are shared between the resident map and the requests that use them; the last owner
 // destroys the plan (an evicted plan stays alive until its queued and running requests finish).
@@ -70,6 +122,8 @@ struct Request {
   double* u = nullptr;
   double t_submit = 0.0, t_admit = 0.0;
   size_t foot = 0;  // bytes charged: the solve's workspace (+ staging when others ride along)
+  size_t off = 0;   // arena offset of the workspace (set at admission)
+  hipEvent_t ready = nullptr;  // recorded on the submitter's stream: f is written
   std::vector<std::unique_ptr<Request>> riders;  // same-plan requests solved with this one
 };
 
@@ -86,8 +140,7 @@ inline size_t batch_foot(helm_plan* p, int total, long long npts) {
 struct Slot {
   std::thread worker;
   hipStream_t stream = nullptr;
-  void* ws = nullptr;
-  size_t ws_cap = 0;
+  void* ws = nullptr;            // the running job's workspace (inside the arena)
   std::unique_ptr<Request> job;  // assigned request (null when idle)
   std::condition_variable cv;
 };
@@ -99,6 +152,11 @@ struct helm_server {
   double max_bypass = 0.0;
   helm_opts opts{};
   int device = 0;
+  helm::DevAlloc alloc;     // allocator of the arena (opts.alloc, else hipMalloc)
+  unsigned char* arena_mem = nullptr;
+  size_t arena_bytes = 0;
+  Arena arena;              // guarded by mu
+  std::vector<hipEvent_t> events;  // idle submit events, guarded by mu
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_done;
@@ -135,15 +193,19 @@ struct helm_server {
         Pending operator[](size_t i) const { return {q[i]->t_submit, q[i]->foot}; }
         Pending front() const { return (*this)[0]; }
       } view{queue};
-      const int i = pick_next(view, free_slots, used, budget, now(), max_bypass);
+      const size_t largest = arena.largest();
+      auto fits = [&](size_t foot) { return Arena::round(foot) <= largest; };
+      const int i = pick_next(view, free_slots, fits, now(), max_bypass);
       if (i < 0) return;
       std::unique_ptr<Request> r = std::move(queue[i]);
       queue.erase(queue.begin() + i);
       r->t_admit = now();
-      add_riders(r.get());
+      add_riders(r.get(), largest);
+      r->off = arena.take(r->foot);  // fits: checked against the largest free range above
       used += r->foot;
       for (auto& s : slots)
         if (!s->job) {
+          s->ws = arena_mem + r->off;
           s->job = std::move(r);
           s->cv.notify_one();
           break;
@@ -154,7 +216,7 @@ struct helm_server {
   // Pull queued requests on r's plan into r's solve while the right-hand sides fit one solve
   // (64) and the grown footprint fits the budget.  Riders pass requests queued before them only
   // while the head of the queue has waited less than max_bypass (or is itself the rider).
-  void add_riders(Request* r) {
+  void add_riders(Request* r, size_t largest) {
     int total = r->nrhs;
     const double t = now();
     for (size_t j = 0; j < queue.size();) {
@@ -165,7 +227,7 @@ struct helm_server {
         continue;
       }
       const size_t grown = batch_foot(r->plan.get(), total + q.nrhs, r->npts);
-      if (grown == 0 || used + grown > budget) break;
+      if (grown == 0 || Arena::round(grown) > largest) break;
       r->foot = grown;
       total += q.nrhs;
       queue[j]->t_admit = t;
@@ -181,6 +243,13 @@ struct helm_server {
     std::vector<Request*> reqs{&r};
     for (auto& q : r.riders) reqs.push_back(q.get());
     std::vector<helm_status> out(reqs.size(), HELM_OK);
+    // every request's right-hand side is complete once its submitter's stream reaches the
+    // point recorded at submit
+    for (Request* q : reqs)
+      if (q->ready && hipStreamWaitEvent(s.stream, q->ready, 0) != hipSuccess) {
+        std::fill(out.begin(), out.end(), HELM_EDEVICE);
+        return out;
+      }
     auto one = [&](Request& q) -> helm_status {
       helm_status st = helm_solve(q.plan.get(), q.f, q.u, q.nrhs, q.sigma.data(), s.ws, s.stream, &info);
       if (st == HELM_OK && helm::wait_stream(s.stream) != hipSuccess) st = HELM_EDEVICE;
@@ -239,18 +308,7 @@ struct helm_server {
       }
       Request& r = **jp;
       helm_info info{};
-      helm_status st = HELM_OK;
-      if (s.ws_cap < r.foot) {
-        if (s.ws) (void)hipFree(s.ws);
-        s.ws = nullptr;
-        s.ws_cap = 0;
-        if (hipMalloc(&s.ws, r.foot) == hipSuccess)
-          s.ws_cap = r.foot;
-        else
-          st = HELM_ENOMEM;
-      }
-      std::vector<helm_status> sts(1 + r.riders.size(), st);
-      if (st == HELM_OK) sts = run(r, s, info);
+      std::vector<helm_status> sts = run(r, s, info);
       const double t_done = now();
       std::vector<helm_request_record> recs;
       for (size_t i = 0; i < sts.size(); ++i) {
@@ -268,14 +326,23 @@ struct helm_server {
         rec.batch = static_cast<int>(sts.size());
         recs.push_back(rec);
       }
+      std::unique_ptr<Request> finished;
       {
         std::lock_guard<std::mutex> lk(mu);
         used -= r.foot;
-        s.job.reset();
+        arena.give(r.off, r.foot);
+        if (r.ready) events.push_back(r.ready);
+        for (auto& q : r.riders)
+          if (q->ready) events.push_back(q->ready);
+        s.ws = nullptr;
+        finished = std::move(s.job);
         for (auto& rec : recs) done.push_back(rec);
         completed += static_cast<long long>(recs.size());
         admit_locked();
       }
+      // released outside the lock: dropping the last reference to an evicted plan frees its
+      // device memory, possibly through the caller's allocator callback
+      finished.reset();
       cv_done.notify_all();
     }
   }
@@ -307,6 +374,14 @@ extern "C" helm_status helm_server_create(size_t hbm_budget_bytes, int slots, do
   if (opts) s->opts = *opts;
   if (hipGetDevice(&s->device) != hipSuccess) return HELM_EDEVICE;
   s->t0 = std::chrono::steady_clock::now();
+  s->alloc = helm::DevAlloc::from(s->opts);
+  if (!s->alloc.valid()) return HELM_EINVAL;
+  // the whole budget as one arena: the server holds exactly this much device memory
+  s->arena_bytes = Arena::round(hbm_budget_bytes);
+  void* mem = nullptr;
+  if (s->alloc.get(&mem, s->arena_bytes) != hipSuccess) return HELM_ENOMEM;
+  s->arena_mem = static_cast<unsigned char*>(mem);
+  s->arena.reset(s->arena_bytes);
   for (int k = 0; k < slots; ++k) {
     auto sl = std::make_unique<Slot>();
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) return HELM_EDEVICE;
@@ -319,7 +394,7 @@ extern "C" helm_status helm_server_create(size_t hbm_budget_bytes, int slots, do
 }
 
 extern "C" helm_status helm_server_submit(helm_server* s, const helm_grid* grid, const helm_bc* bc, const double* sigma,
-                                          int nrhs, const double* f, double* u, long long id) {
+                                          int nrhs, const double* f, double* u, long long id, void* stream) {
   if (!s || !grid || !bc || !sigma || !f || !u || nrhs < 1 || nrhs > 64) return HELM_EINVAL;
   const double t_submit = s->now();
   PlanRef plan;
@@ -360,7 +435,20 @@ extern "C" helm_status helm_server_submit(helm_server* s, const helm_grid* grid,
   r->t_submit = t_submit;
   helm_status st = helm_workspace_size(plan.get(), nrhs, &r->foot);
   if (st != HELM_OK) return st;
-  if (r->foot > s->budget) return HELM_EINVAL;
+  if (Arena::round(r->foot) > s->arena_bytes) return HELM_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->events.empty()) {
+      r->ready = s->events.back();
+      s->events.pop_back();
+    }
+  }
+  if (!r->ready && hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess) return HELM_EDEVICE;
+  if (hipEventRecord(r->ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->events.push_back(r->ready);
+    return HELM_EDEVICE;
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->queue.push_back(std::move(r));
@@ -417,9 +505,11 @@ extern "C" void helm_server_destroy(helm_server* s) {
   for (auto& sl : s->slots) sl->cv.notify_all();
   for (auto& sl : s->slots) {
     if (sl->worker.joinable()) sl->worker.join();
-    if (sl->ws) (void)hipFree(sl->ws);
+    if (sl->stream) (void)hipStreamSynchronize(sl->stream);
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
   }
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  s->alloc.put(s->arena_mem, s->arena_bytes);
   s->plans.clear();
   delete s;
 }
@@ -465,7 +555,8 @@ extern "C" helm_status helm_sched_simulate(int n, const double* arrival, const d
     }
     while (next < n && arrival[next] <= now) q.idx.push_back(next++);
     for (;;) {
-      const int i = pick_next(q, slots - static_cast<int>(running.size()), used, budget, now, max_bypass);
+      auto fits = [&](size_t f) { return used + f <= budget; };
+      const int i = pick_next(q, slots - static_cast<int>(running.size()), fits, now, max_bypass);
       if (i < 0) break;
       const int r = q.idx[i];
       q.idx.erase(q.idx.begin() + i);

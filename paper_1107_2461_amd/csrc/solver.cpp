@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
+#include "alloc.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -28,11 +29,41 @@ using namespace helm;
 
 namespace {
 
+// Device blocks owned by one object, released (on its device, after a device synchronization,
+// since enqueued work may still read them) through the allocator that made them.
+struct DevBlocks {
+  DevAlloc alloc;
+  int device = 0;
+  std::vector<std::pair<void*, size_t>> blocks;
+  template <typename T>
+  hipError_t upload(T** dst, const T* src, size_t count) {
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    void* p = nullptr;
+    hipError_t e = alloc.get(&p, bytes);
+    if (e != hipSuccess) return e;
+    blocks.push_back({p, bytes});
+    *dst = static_cast<T*>(p);
+    if (count) e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+  }
+  ~DevBlocks() {
+    if (blocks.empty()) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    if (alloc.alloc) (void)hipDeviceSynchronize();  // a caller's allocator may reuse the block at once
+    for (auto& b : blocks) alloc.put(b.first, b.second);
+    (void)hipSetDevice(cur);
+  }
+};
+
 // Device copy of one axis' operator and eigenbasis.  Shared between plans through a
-// reference-counted cache keyed by the axis definition (faces, location, walls, device).
+// reference-counted cache keyed by the axis definition (faces, location, walls, device,
+// allocator).
 struct DevAxis {
   Axis1D host;
-  std::string key;           // cache key (faces, location, walls, device)
+  std::string key;           // cache key (faces, location, walls, device, allocator)
+  DevBlocks mem;             // every device buffer below
   int device = 0;
   double* lam = nullptr;     // m eigenvalues
   double* coef = nullptr;    // 3m: lower, diag, upper rows of A
@@ -43,19 +74,6 @@ struct DevAxis {
   double* Einv = nullptr;    // m*m row-major
   void* sw[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][fwd, inv]
   void* sw3[2] = {nullptr, nullptr};  // split-BF16 pieces [fwd, inv]
-  ~DevAxis() {
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(device);
-    for (double* p : {lam, coef, kdiag, koff, vol, E, Einv})
-      if (p) (void)hipFree(p);
-    for (auto& pr : sw)
-      for (void* p : pr)
-        if (p) (void)hipFree(p);
-    for (void* p : sw3)
-      if (p) (void)hipFree(p);
-    (void)hipSetDevice(cur);
-  }
 };
 
 std::mutex g_cache_mu;
@@ -73,27 +91,21 @@ helm_status from_hip(hipError_t e) {
   return HELM_EDEVICE;
 }
 
-template <typename T>
-hipError_t upload(T** dst, const T* src, size_t count) {
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(count, 1) * sizeof(T));
-  if (e != hipSuccess) return e;
-  if (count) e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
-  return e;
-}
-
-std::string axis_key(int n, const double* faces, int loc, int lo, int hi, int device) {
+std::string axis_key(int n, const double* faces, int loc, int lo, int hi, int device, const DevAlloc& al) {
   std::string k(reinterpret_cast<const char*>(faces), sizeof(double) * (n + 1));
   k.push_back(static_cast<char>(loc));
   k.push_back(static_cast<char>(lo));
   k.push_back(static_cast<char>(hi));
   k.append(reinterpret_cast<const char*>(&device), sizeof(int));
+  k.append(al.key());
   return k;
 }
 
-helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::shared_ptr<DevAxis>& out) {
+helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, const DevAlloc& al,
+                     std::shared_ptr<DevAxis>& out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
-  const std::string key = axis_key(n, faces, loc, lo, hi, dev);
+  const std::string key = axis_key(n, faces, loc, lo, hi, dev, al);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
@@ -105,6 +117,8 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
   auto ax = std::make_shared<DevAxis>();
   ax->device = dev;
   ax->key = key;
+  ax->mem.alloc = al;
+  ax->mem.device = dev;
   Axis1D& h = ax->host;
   if (!build_operator_1d(n, faces, loc, lo, hi, h).empty()) return HELM_EINVAL;
   if (h.m > 512) return HELM_EINVAL;
@@ -117,20 +131,21 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
     coef[3 * i + 2] = h.upper[i];
   }
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = upload(&ax->lam, h.lam.data(), m);
-  if (e == hipSuccess) e = upload(&ax->coef, coef.data(), coef.size());
-  if (e == hipSuccess) e = upload(&ax->kdiag, h.k_diag.data(), m);
-  if (e == hipSuccess) e = upload(&ax->koff, h.k_off.data(), h.k_off.size());
-  if (e == hipSuccess) e = upload(&ax->vol, h.vol.data(), m);
-  if (e == hipSuccess) e = upload(&ax->E, h.E.data(), h.E.size());
-  if (e == hipSuccess) e = upload(&ax->Einv, h.Einv.data(), h.Einv.size());
+  DevBlocks& mem = ax->mem;
+  if (e == hipSuccess) e = mem.upload(&ax->lam, h.lam.data(), m);
+  if (e == hipSuccess) e = mem.upload(&ax->coef, coef.data(), coef.size());
+  if (e == hipSuccess) e = mem.upload(&ax->kdiag, h.k_diag.data(), m);
+  if (e == hipSuccess) e = mem.upload(&ax->koff, h.k_off.data(), h.k_off.size());
+  if (e == hipSuccess) e = mem.upload(&ax->vol, h.vol.data(), m);
+  if (e == hipSuccess) e = mem.upload(&ax->E, h.E.data(), h.E.size());
+  if (e == hipSuccess) e = mem.upload(&ax->Einv, h.Einv.data(), h.Einv.size());
   for (int p = 0; p < 3 && e == hipSuccess; ++p) {
     const Prec pr = static_cast<Prec>(p);
     const size_t bytes = swizzled_bytes(pr, m);
     std::vector<unsigned char> buf(bytes);
     for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
       swizzle_operand(pr, m, dir == 0 ? h.Einv.data() : h.E.data(), buf.data());
-      e = upload(reinterpret_cast<unsigned char**>(&ax->sw[p][dir]), buf.data(), bytes);
+      e = mem.upload(reinterpret_cast<unsigned char**>(&ax->sw[p][dir]), buf.data(), bytes);
     }
   }
   if (e == hipSuccess) {
@@ -138,7 +153,7 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, std::s
     std::vector<unsigned char> buf(bytes);
     for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
       swizzle_bf16x3(m, dir == 0 ? h.Einv.data() : h.E.data(), buf.data());
-      e = upload(reinterpret_cast<unsigned char**>(&ax->sw3[dir]), buf.data(), bytes);
+      e = mem.upload(reinterpret_cast<unsigned char**>(&ax->sw3[dir]), buf.data(), bytes);
     }
   }
   if (e != hipSuccess) return from_hip(e);
@@ -164,15 +179,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Device buffer freed (on its device) with its last owner.
 struct DevBuf {
   double* p = nullptr;
-  int device = 0;
-  ~DevBuf() {
-    if (!p) return;
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(device);
-    (void)hipFree(p);
-    (void)hipSetDevice(cur);
-  }
+  DevBlocks mem;
 };
 
 // lambda_x[a] + lambda_y[b] per (x axis, y axis) pair, summed in FP64 and shared by every plan
@@ -191,8 +198,9 @@ helm_status get_lamxy(const DevAxis& X, const DevAxis& Y, std::shared_ptr<DevBuf
   for (int b = 0; b < my; ++b)
     for (int a = 0; a < mx; ++a) t[static_cast<size_t>(b) * mx + a] = X.host.lam[a] + Y.host.lam[b];
   auto buf = std::make_shared<DevBuf>();
-  buf->device = X.device;
-  const hipError_t e = upload(&buf->p, t.data(), t.size());
+  buf->mem.device = X.device;
+  buf->mem.alloc = X.mem.alloc;
+  const hipError_t e = buf->mem.upload(&buf->p, t.data(), t.size());
   if (e != hipSuccess) return from_hip(e);
   if (g_pair_cache.size() >= 1024) purge_expired(g_pair_cache);
   g_pair_cache[key] = buf;
@@ -324,6 +332,9 @@ void helm_default_opts(helm_opts* o) {
   o->ir_tol = 1e-11;
   o->max_sweeps = 12;
   o->null_mode = HELM_NULL_PROJECT;
+  o->alloc = nullptr;
+  o->dealloc = nullptr;
+  o->alloc_ctx = nullptr;
 }
 
 const char* helm_status_str(helm_status s) {
@@ -368,6 +379,7 @@ static bool valid_opts(const helm_opts& o) {
   if (o.method != HELM_TPF && o.method != HELM_TPT_Z) return false;
   if (o.null_mode != HELM_NULL_PROJECT && o.null_mode != HELM_NULL_PAPER_EQ28) return false;
   if (!(o.ir_tol >= 0.0) || o.max_sweeps < 1) return false;
+  if (!DevAlloc::from(o).valid()) return false;
   // The Thomas path runs in FP64 only.
   if (o.method == HELM_TPT_Z && o.precision != HELM_FP64) return false;
   return true;
@@ -405,7 +417,8 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
   bool alln = true;
   for (int d = 0; d < 3; ++d) {
     if (!grid->faces[d]) return HELM_EINVAL;
-    const helm_status s = get_axis(grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d], p->ax[d]);
+    const helm_status s =
+        get_axis(grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d], DevAlloc::from(o), p->ax[d]);
     if (s != HELM_OK) return s;
     p->m[d] = p->ax[d]->host.m;
     alln = alln && p->ax[d]->host.null_mode;
@@ -634,7 +647,7 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
                                   void* ws, void* stream, helm_info* info) {
   if (!p || !f || !u || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
   if (p->refined() && f == u) return HELM_EINVAL;
-  size_t total, off_a, off_b, off_n, off_m, off_c;
+  size_t total = 0, off_a = 0, off_b = 0, off_n = 0, off_m = 0, off_c = 0;
   workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n, &off_m, &off_c);
   if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0) return HELM_EINVAL;
   double sig[kMaxRhs];

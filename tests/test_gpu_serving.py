@@ -1,14 +1,17 @@
 """GPU tests of the continuous-batching server.
 
 Each request's result in the mix must equal the same request solved alone (the same kernels
-on the same data: bitwise equality is expected, and at worst the solver tolerance); the
+on the same data: bitwise equality is expected, and at worst the solver tolerance) and the
+CPU FP64 oracle's solution of its system (FP64 <= 1e-12, refined split-BF16 <= 1e-10); the
 device-workspace budget is respected at every instant; requests overlap in time when the
 budget and slots allow it, and are serialised when the budget admits only one at a time.
+Right-hand sides come from the seeded generators of workloads.py.
 """
 import numpy as np
 import pytest
 
 import workloads
+from oracle import solvers
 
 pytestmark = pytest.mark.gpu
 
@@ -31,11 +34,17 @@ def _requests(torch, n, seed, grids=GRIDS):
     out = []
     for r in reqs:
         prob = workloads.serving_problem(r)
-        g = torch.Generator(device="cuda").manual_seed(r["rhs_seed"])
-        nx, ny, nz = prob.shape_xyz
-        f = torch.randn((r["nrhs"], nz, ny, nx), generator=g, device="cuda", dtype=torch.float64)
+        f = torch.from_numpy(workloads.rhs_normal(r["rhs_seed"], r["nrhs"], prob.shape_xyz)).to("cuda")
         out.append((r, prob, f))
     return out
+
+
+def _oracle_err(prob, f, u):
+    """Largest per-RHS relative 2-norm error of u against the oracle's sparse-LU solution."""
+    fn = f.cpu().numpy()
+    ref, _ = solvers.solve_problem(prob.faces, prob.sigma, fn, prob.loc, prob.bc_lo, prob.bc_hi, method="splu")
+    un = u.cpu().numpy()
+    return max(solvers.rel_err(un[r], ref[r]) for r in range(fn.shape[0]))
 
 
 def _run_server(torch, reqs, precision, budget, slots, warm=True):
@@ -94,11 +103,18 @@ def test_mix_equals_alone_and_overlaps(torch, precision):
     assert overl > 0
     for x in recs:
         assert x["t_submit"] <= x["t_admit"] <= x["t_done"]
-    # cold plans, ragged grids, mixed walls, Laplace requests
+    # cold plans, ragged grids, mixed walls, Laplace requests: each served result equals the
+    # request alone and the oracle's solution
     small = _requests(torch, 16, seed=7)
     outs_s, _ = _run_server(torch, small, precision, budget=64 << 20, slots=4, warm=False)
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    worst = 0.0
     for r, prob, f in small:
         assert _same(torch, _alone(torch, prob, f, precision), outs_s[r["rid"]]), r
+        err = _oracle_err(prob, f, outs_s[r["rid"]])
+        worst = max(worst, err)
+        assert err <= tol, (r, err)
+    print(f"{precision}: served small-grid mix vs oracle, worst relative error {worst:.2e}")
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3_ir", 1e-10)])
@@ -133,6 +149,12 @@ def test_same_plan_requests_ride_along(torch, precision, tol):
         ua = plan.solve(f, sigma=sig)
         torch.cuda.synchronize()
         assert float((ua - us[i]).norm() / ua.norm()) <= tol, (i, precision)
+        fn = f.cpu().numpy()
+        un = us[i].cpu().numpy()
+        for r in range(k):   # each right-hand side with its own shift, against the oracle
+            ref, _ = solvers.solve_problem(prob.faces, sig[r], fn[r:r + 1], prob.loc, prob.bc_lo, prob.bc_hi,
+                                           method="splu")
+            assert solvers.rel_err(un[r], ref[0]) <= tol, (i, r, precision)
 
 
 def test_tight_budget_serialises(torch):
@@ -208,3 +230,93 @@ def test_resident_plans_bounded_lru(torch):
     srv.close()
     assert st["plan_hits"] == 1 and st["plan_misses"] == N + 1
     assert len(recs) == N + 2 and all(r["status"] == 0 for r in recs)
+
+
+def test_submit_waits_for_the_callers_stream(torch):
+    """f is written by a long torch kernel on the caller's stream right before submit; the
+    solve must see the written values (the server waits for an event recorded at submit)."""
+    from paper_1107_2461_amd import Server
+    prob = workloads.box_problem((96, 80, 64), 1.5, 2.0)
+    nx, ny, nz = prob.shape_xyz
+    src = torch.from_numpy(workloads.rhs_normal(91, 2, prob.shape_xyz)).to("cuda")
+    big = torch.randn((4096, 4096), dtype=torch.float64, device="cuda")
+    srv = Server(1 << 30, slots=2)
+    outs = []
+    for rep in range(3):
+        f = torch.zeros_like(src)
+        # queue a few large products, then the write of f, all on the current stream; nothing
+        # is synchronized before submit
+        acc = big
+        for _ in range(4):
+            acc = acc @ big / 4096.0
+        f.copy_(src + 0.0 * acc[0, 0])
+        u = torch.empty_like(f)
+        srv.submit(rep, prob.faces, f, u, [2.0, 2.0])
+        outs.append((f, u))
+    srv.drain()
+    srv.close()
+    torch.cuda.synchronize()
+    ua = _alone(torch, prob, src, "fp64")
+    for f, u in outs:
+        assert torch.equal(u, ua) or float((u - ua).norm() / ua.norm()) <= 1e-12
+
+
+def test_server_holds_exactly_its_budget(torch):
+    """The workspace arena is the budget, taken once from the allocator at creation: a stream of
+    requests of several sizes allocates nothing more, and destroying the server returns it."""
+    from paper_1107_2461_amd import Server, torch_allocator
+    al = torch_allocator()
+    reqs = _requests(torch, 12, seed=9)
+    budget = 48 << 20
+    torch.cuda.synchronize()
+    m0, b0 = torch.cuda.memory_allocated(), al.blocks()
+    srv = Server(budget, slots=3, allocator=al)
+    m1 = torch.cuda.memory_allocated()
+    assert al.blocks() == b0 + 1 and m1 - m0 >= budget
+    for rnd in range(2):
+        outs = {}
+        for r, prob, f in reqs:
+            u = torch.empty_like(f)
+            outs[r["rid"]] = u
+            srv.submit(r["rid"], prob.faces, f, u, [prob.sigma] * f.shape[0], prob.bc_lo, prob.bc_hi)
+        srv.drain()
+        recs = srv.poll(max_records=64)
+        assert len(recs) == len(reqs) and all(x["status"] == 0 for x in recs)
+        # device memory beyond the arena: only the plans' eigenbases (shared per axis, resident)
+        if rnd == 0:
+            m_plans = torch.cuda.memory_allocated()
+        else:
+            assert torch.cuda.memory_allocated() == m_plans
+    for r, prob, f in reqs:
+        assert _same(torch, _alone(torch, prob, f, "fp64"), outs[r["rid"]])
+    srv.close()
+    del outs                      # the outputs were allocated after m0 was taken
+    torch.cuda.synchronize()
+    assert al.blocks() == b0 and torch.cuda.memory_allocated() == m0
+
+
+def test_plan_memory_from_torch_allocator(torch):
+    """A plan built with the torch allocator keeps its device memory in torch's caching allocator
+    (memory_allocated rises by at least its FP64 eigenbases) and solves exactly as a plan on
+    hipMalloc memory; destroying it returns the memory."""
+    from paper_1107_2461_amd import Plan, torch_allocator
+    al = torch_allocator()
+    n = (40, 36, 44)
+    faces = tuple(workloads.stretched_faces(n[d], 1.3 + 0.1 * d) for d in range(3))
+    f = torch.from_numpy(workloads.rhs_uniform(93, 2, n)).to("cuda")
+    for precision in ("fp64", "bf16x3_ir"):
+        torch.cuda.synchronize()
+        m0, b0 = torch.cuda.memory_allocated(), al.blocks()
+        plan = Plan(faces, (0, 1, 0), (0, 0, 1), 0.5, precision=precision, allocator=al)
+        m1 = torch.cuda.memory_allocated()
+        assert al.blocks() > b0
+        assert m1 - m0 >= sum(2 * k * k * 8 for k in n), (m1 - m0)
+        u = plan.solve(f)
+        ref = Plan(faces, (0, 1, 0), (0, 0, 1), 0.5, precision=precision).solve(f)
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref)
+        del plan
+        import gc
+        gc.collect()
+        torch.cuda.synchronize()
+        assert al.blocks() == b0 and torch.cuda.memory_allocated() == m0
