@@ -28,7 +28,12 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 6}
+# Datasheet dense matrix peaks per contraction dtype.  Split-BF16 products contract on the BF16
+# matrix cores, so they are priced against the BF16 peak with their algorithmic flops (2N per
+# point); the six partial products they issue per algorithmic product are reported separately
+# (issued_flops_factor), never folded into the peak.
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+ISSUED_FLOPS_FACTOR = {"fp64": 1, "fp32": 1, "bf16": 1, "bf16x3": 6}
 ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}
 RIDGE = {k: v * 1e12 / (HBM_PEAK_GBS * 1e9) for k, v in MFMA_PEAK_TFLOPS.items()}
 MODE_STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv", "x_fwd_rhs", "z_inv_u")
@@ -68,11 +73,13 @@ def stage_roofline(stage, ms, launches, N, npts, prec):
         if stage == last and prec != "fp64":
             byts = (es + 16) * npts          # read du (low), read + write u (FP64)
         ai = flops / byts
+        extra = dict(avg_us=avg_s * 1e6, algorithmic_flops=flops, algorithmic_bytes=byts,
+                     algorithmic_tflops=flops / avg_s / 1e12, issued_flops_factor=ISSUED_FLOPS_FACTOR[prec],
+                     issued_tflops=ISSUED_FLOPS_FACTOR[prec] * flops / avg_s / 1e12)
         if ai >= RIDGE[prec]:
             return dict(bound="mfma", achieved=flops / avg_s / 1e12, peak=MFMA_PEAK_TFLOPS[prec], unit="TFLOP/s",
-                        avg_us=avg_s * 1e6, algorithmic_flops=flops, algorithmic_bytes=byts)
-        return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", avg_us=avg_s * 1e6,
-                    algorithmic_flops=flops, algorithmic_bytes=byts)
+                        **extra)
+        return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", **extra)
     # split-BF16: the first refinement sweep reads the FP32 first solve (two sweeps in the
     # workloads measured here); other paths read u in FP64
     u_bytes = 4 if prec == "bf16x3" else 8
@@ -257,10 +264,12 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
             idx = np.array(g["idx"])
             errs.append(float(np.abs(uh[r, idx] - np.array(g["u"])).max() / g["norminf"]))
         res["err_vs_oracle_samples"] = max(errs)
+    # the library's own FP64 operator (helm_apply): a diagnostic, not an accuracy claim (that is
+    # err_vs_oracle_samples above and the GPU tests against the oracle's assembled operator)
     hu = plan.apply(u)
     fr = f_dev.reshape(nrhs, -1)
     rr = (fr - hu.reshape(nrhs, -1)).norm(dim=1) / fr.norm(dim=1)
-    res["rel_residual"] = float(rr.max())
+    res["rel_residual_helm_apply"] = float(rr.max())
     res["stages"] = st
     res["dominant"] = dict(kernel=dom, launches_per_step=dn / steps, **dom_rl)
     res["precision"] = lowp
@@ -327,7 +336,7 @@ def sustained_peak(prec, bound):
     if bound == "hbm":
         return pk.get("hbm_copy", {}).get("gbps")
     if prec == "bf16x3":
-        return pk["bf16"]["tflops"] / 6 if "bf16" in pk else None
+        return pk["bf16"]["tflops"] if "bf16" in pk else None
     return pk.get(prec, {}).get("tflops")
 
 
@@ -646,7 +655,7 @@ def run_pressure(torch, args):
         results[path] = run_path(torch, prob, f_dev, path, args.steps, args.warmup, golden, 1)
         log(f"[bench] {path}: {results[path]['ms_per_step']:.3f} ms/solve, err "
             f"{results[path].get('err_vs_oracle_samples')}")
-    ok = {k: v for k, v in results.items() if v.get("err_vs_oracle_samples", v["rel_residual"]) <= 1e-10}
+    ok = {k: v for k, v in results.items() if v.get("err_vs_oracle_samples", v["rel_residual_helm_apply"]) <= 1e-10}
     best = max(ok or results, key=lambda k: results[k]["pts_per_s"])
     b = results[best]
     d = b["dominant"]
@@ -1042,7 +1051,7 @@ def main():
         results[path] = run_path(torch, prob, f_dev, path, args.steps, args.warmup, golden, nrhs)
         log(f"[bench] {path}: {results[path]['ms_per_step']:.3f} ms/step, "
             f"{results[path]['pts_per_s']:.3e} pts/s, err {results[path].get('err_vs_oracle_samples')}")
-    ok = {k: v for k, v in results.items() if v.get("err_vs_oracle_samples", v["rel_residual"]) <= 1e-10}
+    ok = {k: v for k, v in results.items() if v.get("err_vs_oracle_samples", v["rel_residual_helm_apply"]) <= 1e-10}
     best = max(ok, key=lambda k: ok[k]["pts_per_s"]) if ok else max(results, key=lambda k: results[k]["pts_per_s"])
     b = results[best]
     # dominant kernel of the headline path, timed inside the timed region
@@ -1051,6 +1060,14 @@ def main():
     roofline = dict(kernel=dom, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
                     frac=d["frac"], traffic=committed_traffic(b["precision"], dom), avg_us=d["avg_us"],
                     algorithmic_bytes=d.get("algorithmic_bytes"), algorithmic_flops=d.get("algorithmic_flops"))
+    if "algorithmic_tflops" in d:
+        # the contraction's rate beside the bound: algorithmic flops, and the flops the matrix cores
+        # issue (six per algorithmic one for split BF16), each against the contraction dtype's peak
+        pk = MFMA_PEAK_TFLOPS[b["precision"]]
+        roofline.update(algorithmic_tflops=d["algorithmic_tflops"], mfma_peak_tflops=pk,
+                        mfma_frac_algorithmic=d["algorithmic_tflops"] / pk,
+                        issued_flops_factor=d["issued_flops_factor"], issued_tflops=d["issued_tflops"],
+                        mfma_frac_issued=d["issued_tflops"] / pk)
     sp = sustained_peak(b["precision"], d["bound"])
     if sp:
         roofline.update(sustained_peak=sp, frac_of_sustained=d["achieved"] / sp)
