@@ -150,6 +150,22 @@ helm_status helm_workspace_size(const helm_plan* plan, int nrhs, size_t* bytes);
 helm_status helm_solve(helm_plan* plan, const double* f, double* u, int nrhs,
                        const double* sigma_per_rhs, void* ws, void* stream, helm_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): helm_solve with the workspace taken from a
+ * device array the library holds on each GPU (HELM_NOALLOC_MAX_WORKSPACE bytes, created when
+ * the library's code is loaded on that GPU and kept until the process ends) instead of a ws
+ * argument.  Same arguments, results and asynchrony as helm_solve; the call allocates nothing
+ * (no hipMalloc, no pinned memory, no events).  Limits: helm_workspace_size(plan, nrhs) must
+ * be <= HELM_NOALLOC_MAX_WORKSPACE (else EINVAL: e.g. a 256^3 FP64 solve with one right-hand
+ * side needs 128 MiB, a refined split-BF16 one 192 MiB); refined plans must run a fixed sweep
+ * count (ir_tol = 0, else EINVAL: adaptive refinement reads its norms through pinned host
+ * memory); stage timing must be off (else EINVAL).  Every call on one GPU uses that GPU's one
+ * array, so calls that overlap on one GPU (other threads, other streams) race: serialize them.
+ * The array keeps the last call's contents; no call depends on them. */
+#define HELM_NOALLOC_MAX_WORKSPACE ((size_t)256 << 20)
+helm_status helm_solve_noalloc(helm_plan* plan, const double* f, double* u, int nrhs,
+                               const double* sigma_per_rhs, void* stream, helm_info* info);
+
 /* Hu = (sigma I - Lap_h) u with the FP64 7-point operator (the Kronecker sum of eq. 29),
  * device pointers [nrhs][nz][ny][nx]; asynchronous.  Hu must not alias u. */
 helm_status helm_apply(const helm_plan* plan, const double* u, double* Hu, int nrhs,

@@ -205,6 +205,31 @@ class Plan:
             check(st, "helm_solve")
         return u[0] if squeeze else u
 
+    def solve_noalloc(self, f, out=None, sigma=None, stream=None):
+        """helm_solve_noalloc: the solve with the library's static per-GPU workspace (no
+        allocation by the library; refined plans need ir_tol = 0).  out must be given by callers
+        that cannot allocate; None allocates it here with torch."""
+        torch = _torch()
+        squeeze = f.dim() == 3
+        f4 = f.unsqueeze(0) if squeeze else f
+        if f4.dtype != torch.float64 or not f4.is_cuda or not f4.is_contiguous():
+            raise ValueError("f must be a contiguous float64 CUDA tensor")
+        nrhs = f4.shape[0]
+        if tuple(f4.shape[1:]) != self.shape_xyz[::-1]:
+            raise ValueError(f"f shape {tuple(f4.shape)} does not match the plan grid {self.shape_xyz[::-1]}")
+        u = torch.empty_like(f4) if out is None else (out.unsqueeze(0) if out.dim() == 3 else out)
+        sig = None
+        if sigma is not None:
+            sarr = (C.c_double * nrhs)(*[float(s) for s in np.broadcast_to(np.asarray(sigma, float), (nrhs,))])
+            sig = C.cast(sarr, _lib.DP)
+        info = _lib.HelmInfo()
+        st = load().helm_solve_noalloc(self._h, C.c_void_p(f4.data_ptr()), C.c_void_p(u.data_ptr()), nrhs, sig,
+                                       _stream_ptr(stream), C.byref(info))
+        self.last_info = dict(sweeps=info.sweeps, last_correction=info.last_correction,
+                              converged=None if info.converged < 0 else bool(info.converged))
+        check(st, "helm_solve_noalloc")
+        return u[0] if squeeze else u
+
     def apply(self, u, sigma=None, stream=None):
         """Hu with the FP64 7-point operator (helm_apply)."""
         torch = _torch()

@@ -7,6 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhelm.so")
 
+NOALLOC_MAX_WORKSPACE = 256 << 20   # HELM_NOALLOC_MAX_WORKSPACE
 HELM_OK, HELM_EINVAL, HELM_ESINGULAR, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOTCONVERGED, HELM_ENONFINITE = range(7)
 DIRICHLET, NEUMANN = 0, 1
 CELL, FACE = 0, 1
@@ -67,6 +68,7 @@ SIGNATURES = {
                              C.POINTER(P)]),
     "helm_workspace_size": (C.c_int, [P, C.c_int, C.POINTER(C.c_size_t)]),
     "helm_solve": (C.c_int, [P, P, P, C.c_int, DP, P, P, C.POINTER(HelmInfo)]),
+    "helm_solve_noalloc": (C.c_int, [P, P, P, C.c_int, DP, P, C.POINTER(HelmInfo)]),
     "helm_apply": (C.c_int, [P, P, P, C.c_int, DP, P]),
     "helm_get_eigen": (C.c_int, [P, C.c_int, IP, DP, DP, DP]),
     "helm_destroy": (None, [P]),

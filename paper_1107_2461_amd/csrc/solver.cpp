@@ -24,6 +24,7 @@
 #include "alloc.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
+#include "solve_impl.hpp"
 
 using namespace helm;
 
@@ -645,8 +646,20 @@ extern "C" helm_status helm_apply(const helm_plan* p, const double* u, double* H
 
 extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int nrhs, const double* sigma_per_rhs,
                                   void* ws, void* stream, helm_info* info) {
+  return helm::solve_impl(p, f, u, nrhs, sigma_per_rhs, ws, stream, info, false);
+}
+
+int helm::plan_device(const helm_plan* p) { return p ? p->device : -1; }
+
+// The solve sequence shared by helm_solve and helm_solve_noalloc.  noalloc: the call must not
+// allocate anything, so the two paths that create objects on demand are refused (EINVAL):
+// adaptive refinement (its norms are read back through pinned host memory and a per-thread
+// event) and stage timing (its events are created lazily).
+helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs, const double* sigma_per_rhs,
+                             void* ws, void* stream, helm_info* info, bool noalloc) {
   if (!p || !f || !u || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
   if (p->refined() && f == u) return HELM_EINVAL;
+  if (noalloc && (p->prof.on || (p->refined() && p->opts.ir_tol != 0.0))) return HELM_EINVAL;
   size_t total = 0, off_a = 0, off_b = 0, off_n = 0, off_m = 0, off_c = 0;
   workspace_layout(p, nrhs, &total, &off_a, &off_b, &off_n, &off_m, &off_c);
   if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0) return HELM_EINVAL;
