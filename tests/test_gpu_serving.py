@@ -290,7 +290,7 @@ def test_server_holds_exactly_its_budget(torch):
     for r, prob, f in reqs:
         assert _same(torch, _alone(torch, prob, f, "fp64"), outs[r["rid"]])
     srv.close()
-    del outs                      # the outputs were allocated after m0 was taken
+    del outs, u                   # the outputs were allocated after m0 was taken
     torch.cuda.synchronize()
     assert al.blocks() == b0 and torch.cuda.memory_allocated() == m0
 
@@ -304,6 +304,7 @@ def test_plan_memory_from_torch_allocator(torch):
     n = (40, 36, 44)
     faces = tuple(workloads.stretched_faces(n[d], 1.3 + 0.1 * d) for d in range(3))
     f = torch.from_numpy(workloads.rhs_uniform(93, 2, n)).to("cuda")
+    import gc
     for precision in ("fp64", "bf16x3_ir"):
         torch.cuda.synchronize()
         m0, b0 = torch.cuda.memory_allocated(), al.blocks()
@@ -315,8 +316,11 @@ def test_plan_memory_from_torch_allocator(torch):
         ref = Plan(faces, (0, 1, 0), (0, 0, 1), 0.5, precision=precision).solve(f)
         torch.cuda.synchronize()
         assert torch.equal(u, ref)
+        plan._ws.clear()          # the binding's cached solve workspace (a torch tensor of its own)
+        torch.cuda.synchronize()
+        m2 = torch.cuda.memory_allocated()
         del plan
-        import gc
         gc.collect()
         torch.cuda.synchronize()
-        assert al.blocks() == b0 and torch.cuda.memory_allocated() == m0
+        # destroying the plan returns exactly what building it took (other tensors stay)
+        assert al.blocks() == b0 and m2 - torch.cuda.memory_allocated() == m1 - m0
