@@ -180,6 +180,48 @@ helm_status helm_get_eigen(const helm_plan* plan, int axis, int* n, double* lam,
 /* Releases the plan and its device memory (synchronizes the device first). */
 void helm_destroy(helm_plan* plan);
 
+/* ---------------------------------------------------------------------------------------
+ * Cylindrical coordinates (Section 6, eqs. 41-44): (sigma I - Lap_h) u = f with
+ *     Lap u = (1/r) d/dr (r du/dr) + (1/r^2) d^2u/dtheta^2 + d^2u/dz^2
+ * discretized by cell-centred finite volumes (face area times normal derivative; the theta
+ * derivative taken along the arc at the cell-centre radius).  Per eq. 42 the theta and z
+ * operators are eigen-decomposed once; per eq. 44 every (theta mode m, z mode n) pair then
+ * leaves one radial tridiagonal system (A_r + lambda_theta(m) / r^2 + lambda_z(n) + sigma) a = g,
+ * solved by the Thomas algorithm.  FP64 only.
+ *
+ * Layout of every grid function of a cylindrical plan: contiguous float64
+ * [nrhs][n_r][n_z][n_theta], theta fastest, r slowest (the Thomas direction).  helm_solve,
+ * helm_solve_noalloc, helm_apply, helm_workspace_size, helm_get_eigen (axis 0 = theta,
+ * 1 = z, 2 = r: the radial operator of the m = 0 mode) and helm_destroy accept such a plan.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  int n[3];                 /* cells along r, theta, z; r >= 2, z >= 2, theta >= 2 (>= 3 periodic) */
+  const double* faces[3];   /* host, n[d] + 1 strictly increasing face coordinates (copied):
+                               radii r_0 >= 0 (r_0 = 0: the axis, a face of zero area), angles in
+                               radians, axial positions */
+  int theta_periodic;       /* 1: theta closed on itself (the last cell's upper face is the first
+                               cell's lower face; the period is faces[1][n] - faces[1][0]), 0: a
+                               sector with walls per bc */
+} helm_cyl_grid;
+
+/* Builds a cylindrical plan.  bc->lo/hi[0] are the inner and outer radial walls (the inner one
+ * is ignored on the axis), [1] the theta walls of a sector (ignored when periodic), [2] the axial
+ * walls.  opts: precision must be HELM_FP64 (else EINVAL); method is ignored (the Thomas form).
+ * sigma >= 0 (else EINVAL).  Without any Dirichlet wall of nonzero area and with sigma = 0 the
+ * problem is singular: the null mode is handled as in helm_setup (opts->null_mode).  Errors:
+ * EINVAL (as helm_setup, plus the above), ENOMEM, EDEVICE. */
+helm_status helm_cyl_setup(const helm_cyl_grid* grid, const helm_bc* bc, double sigma, const helm_opts* opts,
+                           helm_plan** out);
+
+/* Host-only helpers for the cylindrical axes (kind 0 = radial with walls bc_lo/bc_hi, 1 =
+ * periodic theta): rows of A = V^{-1} K and the control volumes (radial: rc dr), and the
+ * eigen-decomposition as in helm_host_eigen_1d.  A periodic axis couples its last and first
+ * node: lower[0] and upper[m - 1] hold that coupling. */
+helm_status helm_host_operator_cyl(int kind, int n, const double* faces, int bc_lo, int bc_hi, int* m_out,
+                                   double* lower, double* diag, double* upper, double* vol);
+helm_status helm_host_eigen_cyl(int kind, int n, const double* faces, int bc_lo, int bc_hi, int* m_out,
+                                double* lam, double* E, double* Einv);
+
 /* Pressure-Laplacian plan used as the pressure-matrix preconditioner (Section 2 and the
  * Neumann case of Section 3, eq. 28): cell-centred, all walls Neumann, sigma = 0.
  * Equivalent to helm_setup with those arguments and null_mode from opts. */

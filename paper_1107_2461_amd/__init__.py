@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (BF16, BF16_IR, CELL, DIRICHLET, FACE, FP32, FP32_IR, FP64, NEUMANN, NULL_PAPER_EQ28,
                    NULL_PROJECT, TPF, TPT_Z, HelmError, check, load)
 
-__all__ = ["Plan", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
+__all__ = ["Plan", "CylPlan", "host_operator_cyl", "host_eigen_cyl", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
            "NEUMANN", "CELL", "FACE", "FP64", "FP32", "BF16", "FP32_IR", "BF16_IR", "TPF", "TPT_Z",
            "NULL_PROJECT", "NULL_PAPER_EQ28"]
 
@@ -121,8 +121,16 @@ class Plan:
 
     def __init__(self, faces, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, sigma=0.0, loc=(CELL,) * 3,
                  precision="fp64", method="tpf", ir_tol=None, max_sweeps=None, null_mode=NULL_PROJECT,
-                 pressure=False, allocator=None):
+                 pressure=False, allocator=None, _handle=None):
         lib = load()
+        if _handle is not None:            # built by a subclass's own setup call
+            self._h = _handle
+            self.sigma = float(sigma)
+            self.pressure = False
+            self.shape_xyz = tuple(self.eigen(d)[0].shape[0] for d in range(3))
+            self._ws = {}
+            self.last_info = None
+            return
         g, self._faces = _grid(faces, loc)
         opts = _opts(precision, method, ir_tol, max_sweeps, null_mode, allocator)
         h = C.c_void_p()
@@ -276,6 +284,66 @@ class Plan:
         check(lib.helm_get_eigen(self._h, axis, C.byref(n), lam.ctypes.data_as(_lib.DP), E.ctypes.data_as(_lib.DP),
                                  Ei.ctypes.data_as(_lib.DP)), "helm_get_eigen")
         return lam, E, Ei
+
+
+class CylPlan(Plan):
+    """Cylindrical-coordinate plan (helm_cyl_setup; Section 6, eqs. 41-44): FP64, transforms in
+    theta and z and one Thomas solve per radial line.  Grid functions are float64 CUDA tensors
+    [nrhs, n_r, n_z, n_theta] (theta fastest); solve / solve_noalloc / apply as for Plan.
+
+    faces = (r_faces, theta_faces, z_faces); bc_lo / bc_hi = (r, theta, z) walls (the inner r
+    wall is ignored on the axis r_0 = 0, the theta walls when theta_periodic)."""
+
+    def __init__(self, faces, bc_lo=(DIRICHLET,) * 3, bc_hi=(DIRICHLET,) * 3, sigma=0.0, theta_periodic=True,
+                 null_mode=NULL_PROJECT, allocator=None):
+        lib = load()
+        arrs = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
+        g = _lib.HelmCylGrid()
+        for d in range(3):
+            g.n[d] = len(arrs[d]) - 1
+            g.faces[d] = arrs[d].ctypes.data_as(_lib.DP)
+        g.theta_periodic = int(bool(theta_periodic))
+        bc = _lib.HelmBC()
+        for d in range(3):
+            bc.lo[d] = int(bc_lo[d])
+            bc.hi[d] = int(bc_hi[d])
+        opts = _opts("fp64", "tpt", None, None, null_mode, allocator)
+        h = C.c_void_p()
+        check(lib.helm_cyl_setup(C.byref(g), C.byref(bc), float(sigma), C.byref(opts), C.byref(h)), "helm_cyl_setup")
+        self._faces = arrs
+        super().__init__(None, sigma=sigma, _handle=h)
+        # plan axes are (theta, z, r); the tensor shape is (nrhs, n_r, n_z, n_theta)
+        self.shape_rtz = (self.shape_xyz[2], self.shape_xyz[0], self.shape_xyz[1])
+
+
+def host_operator_cyl(kind, faces, bc_lo=DIRICHLET, bc_hi=DIRICHLET):
+    """Rows (lower, diag, upper) of A = V^{-1} K and control volumes of a cylindrical axis from the
+    library's host code: kind 0 = radial (volumes rc dr), 1 = periodic theta (lower[0] and
+    upper[-1] couple the two ends)."""
+    lib = load()
+    fa = np.ascontiguousarray(np.asarray(faces, dtype=np.float64))
+    n = len(fa) - 1
+    out = [np.zeros(n) for _ in range(4)]
+    m = C.c_int()
+    check(lib.helm_host_operator_cyl(int(kind), n, fa.ctypes.data_as(_lib.DP), bc_lo, bc_hi, C.byref(m),
+                                     *[o.ctypes.data_as(_lib.DP) for o in out]), "helm_host_operator_cyl")
+    return tuple(o[:m.value] for o in out)
+
+
+def host_eigen_cyl(kind, faces, bc_lo=DIRICHLET, bc_hi=DIRICHLET):
+    """(lam, E, Einv) of a cylindrical axis (kind 0 radial, 1 periodic) from the library's host code."""
+    lib = load()
+    fa = np.ascontiguousarray(np.asarray(faces, dtype=np.float64))
+    n = len(fa) - 1
+    lam = np.zeros(n)
+    E = np.zeros(n * n)
+    Ei = np.zeros(n * n)
+    m = C.c_int()
+    check(lib.helm_host_eigen_cyl(int(kind), n, fa.ctypes.data_as(_lib.DP), bc_lo, bc_hi, C.byref(m),
+                                  lam.ctypes.data_as(_lib.DP), E.ctypes.data_as(_lib.DP),
+                                  Ei.ctypes.data_as(_lib.DP)), "helm_host_eigen_cyl")
+    mm = m.value
+    return lam[:mm], E[:mm * mm].reshape(mm, mm), Ei[:mm * mm].reshape(mm, mm)
 
 
 def host_operator_1d(faces, loc=CELL, bc_lo=DIRICHLET, bc_hi=DIRICHLET):

@@ -26,6 +26,10 @@ class HelmGrid(C.Structure):
     _fields_ = [("n", C.c_int * 3), ("faces", C.POINTER(C.c_double) * 3), ("loc", C.c_int * 3)]
 
 
+class HelmCylGrid(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("faces", C.POINTER(C.c_double) * 3), ("theta_periodic", C.c_int)]
+
+
 class HelmBC(C.Structure):
     _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3)]
 
@@ -98,6 +102,10 @@ SIGNATURES = {
     "helm_server_destroy": (None, [P]),
     "helm_sched_simulate": (C.c_int, [C.c_int, DP, DP, C.POINTER(C.c_size_t), C.c_int, C.c_size_t, C.c_double, DP,
                                       DP]),
+    "helm_cyl_setup": (C.c_int, [C.POINTER(HelmCylGrid), C.POINTER(HelmBC), C.c_double, C.POINTER(HelmOpts),
+                                 C.POINTER(P)]),
+    "helm_host_operator_cyl": (C.c_int, [C.c_int, C.c_int, DP, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
+    "helm_host_eigen_cyl": (C.c_int, [C.c_int, C.c_int, DP, C.c_int, C.c_int, IP, DP, DP, DP]),
     "helm_host_operator_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
     "helm_host_eigen_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP]),
 }

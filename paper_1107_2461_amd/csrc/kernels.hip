@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "mode_common.hpp"
@@ -146,16 +147,21 @@ size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs) {
   return static_cast<size_t>(2LL * thomas_nseg(nz) * thomas_lanes(nl)) * sizeof(double);
 }
 
+// CYL: the cylindrical line operator K_r + lam_theta G + (lam_z + sigma) V_r (eq. 44).
+template <bool CYL>
 __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArgs a, double* __restrict__ chk) {
-  extern __shared__ double zrow[];  // K_z diagonal [nz], V_z [nz], K_z off-diagonal [nz] (last = 0)
+  // K_z diagonal [nz], V_z [nz], K_z off-diagonal [nz] (last = 0), and for CYL the metric G [nz]
+  extern __shared__ double zrow[];
   const int nz = a.nz;
   double* sk = zrow;
   double* sv = zrow + nz;
   double* so = zrow + 2 * nz;
+  double* sg = zrow + 3 * nz;
   for (int i = threadIdx.x; i < nz; i += 64) {
     sk[i] = a.kdiag[i];
     sv[i] = a.vol[i];
     so[i] = i < nz - 1 ? a.koff[i] : 0.0;
+    if constexpr (CYL) sg[i] = a.gdiag[i];
   }
   __syncthreads();
   const long long Nn = static_cast<long long>(a.nx) * a.ny;
@@ -170,7 +176,9 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
   const long long n = line - r * Nn;
   if (a.skip_null && n == 0) return;
   const int ax = static_cast<int>(n % a.nx), by = static_cast<int>(n / a.nx);
-  const double c = a.lamx[ax] + a.lamy[by] + a.sigma[r];
+  // diagonal of row k: K_kk + c V_k (+ cg G_k for CYL)
+  const double c = CYL ? a.lamy[by] + a.sigma[r] : a.lamx[ax] + a.lamy[by] + a.sigma[r];
+  const double cg = CYL ? a.lamx[ax] : 0.0;
   const int m = nz / 2;
   const int len = bot ? nz - 1 - m : m;  // rows this lane eliminates: m above the middle, the rest below
   const long long stride = bot ? -Nn : Nn;
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
       const int s = j * kSeg + t;
       const int rw = row_of(s);
       const double vk = sv[rw];
-      dg[t] = sk[rw] + c * vk;
+      dg[t] = CYL ? sk[rw] + c * vk + cg * sg[rw] : sk[rw] + c * vk;
       rh[t] = vk * g[t];
       ko[t] = so[cpl_of(s)];
     }
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
   const double o_t = so[max(m - 1, 0)], o_b = so[m];  // couplings of row m to rows m - 1 and m + 1
   const double mt = o_t * ib_t, mb = o_b * ib_b;
   const double vm = sv[m];
-  const double dm = sk[m] + c * vm - mt * o_t - mb * o_b;
+  const double dm = (CYL ? sk[m] + c * vm + cg * sg[m] : sk[m] + c * vm) - mt * o_t - mb * o_b;
   const double xm = (vm * col0[static_cast<long long>(m) * Nn] - mt * y_t - mb * y_b) / dm;
   if (!bot) col0[static_cast<long long>(m) * Nn] = xm;
   // backward sweep, one segment at a time from the middle outward.  The checkpoint a segment
@@ -292,9 +300,13 @@ hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st) {
   if (nl == 0) return hipSuccess;
   if (a.nz < 1 || a.nz > 2048) return hipErrorInvalidValue;
   const long long blocks = thomas_lanes(nl) / 64;
-  const size_t lds = 3 * static_cast<size_t>(a.nz) * sizeof(double);
-  hipLaunchKernelGGL(k_thomas, dim3(static_cast<unsigned>(blocks)), dim3(64), lds, st, v, a,
-                     static_cast<double*>(chk));
+  const size_t lds = (a.gdiag ? 4 : 3) * static_cast<size_t>(a.nz) * sizeof(double);
+  if (a.gdiag)
+    hipLaunchKernelGGL(k_thomas<true>, dim3(static_cast<unsigned>(blocks)), dim3(64), lds, st, v, a,
+                       static_cast<double*>(chk));
+  else
+    hipLaunchKernelGGL(k_thomas<false>, dim3(static_cast<unsigned>(blocks)), dim3(64), lds, st, v, a,
+                       static_cast<double*>(chk));
   return hipGetLastError();
 }
 
@@ -349,7 +361,9 @@ template <typename T>
 __device__ inline T lane_above(T v, int lane) { return __shfl(v, lane < 63 ? lane + 1 : 63); }
 
 // TU: storage of u (FP64, or FP32 for the first solve's result, which is exact in FP64 once read)
-template <typename TOut, int MODE, typename TU>  // MODE 0: out = H u, 1: out = f - H u
+// CYL: cylindrical operator (x = theta, y = z, z = r): the x term of plane k is scaled by
+// a.xscale[k], and x is periodic when a.xper is set.
+template <typename TOut, int MODE, typename TU, bool CYL = false>  // MODE 0: out = H u, 1: out = f - H u
 __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
                                                  const double* __restrict__ f, TOut* __restrict__ out,
                                                  StencilArgs a, int zchunk, int nzc, int wx, int nbx, int nby) {
@@ -378,7 +392,8 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
   const long long plane = static_cast<long long>(a.nx) * a.ny;
   const long long rbase = static_cast<long long>(r) * plane * a.nz;
   const double cxl = a.cx[3 * ic], cxd = a.cx[3 * ic + 1], cxu = a.cx[3 * ic + 2];
-  const bool hx_lo = ic > 0, hx_hi = ic + 1 < a.nx;
+  const bool xper = CYL && a.xper;
+  const bool hx_lo = xper || ic > 0, hx_hi = xper || ic + 1 < a.nx;
   int jr[JS + 2];  // rows j0-1 .. j0+JS, clamped into the grid
 #pragma unroll
   for (int s = 0; s < JS + 2; ++s) jr[s] = min(max(j0 - 1 + s, 0), a.ny - 1);
@@ -388,7 +403,8 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
     const int j = jr[s + 1];
     cyl[s] = (j0 + s > 0 && j0 + s < a.ny) ? a.cy[3 * j] : 0.0;
     cyu[s] = (j0 + s + 1 < a.ny) ? a.cy[3 * j + 2] : 0.0;
-    dxy[s] = a.sigma[r] + cxd + a.cy[3 * j + 1];
+    // Cartesian: sigma + x and y diagonals; CYL: the x diagonal is added per plane, scaled
+    dxy[s] = CYL ? a.sigma[r] + a.cy[3 * j + 1] : a.sigma[r] + cxd + a.cy[3 * j + 1];
   }
   const TU* ucol = u + rbase + ic;
   auto at = [&](int k, int s) { return ucol + k * plane + static_cast<long long>(jr[s]) * a.nx; };
@@ -406,8 +422,10 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
     for (int s = 0; s < JS; ++s) {
       TU lo = lane_below(uc[s + 1], lane), hi = lane_above(uc[s + 1], lane);
       const TU* p = at(k, s + 1);
-      if (lane == 0 && hx_lo) lo = p[-1];
-      if (lane == 63 && hx_hi) hi = p[1];
+      if (lane == 0 && hx_lo && ic > 0) lo = p[-1];
+      if (lane == 63 && hx_hi && ic + 1 < a.nx) hi = p[1];
+      if (xper && ic == 0) lo = p[a.nx - 1];      // periodic wrap: the last column of the row
+      if (xper && ic == a.nx - 1) hi = p[1 - a.nx];  // and its first
       xs[s] = (hx_lo ? cxl * static_cast<double>(lo) : 0.0) + (hx_hi ? cxu * static_cast<double>(hi) : 0.0);
       fv[s] = MODE == 1 ? f[rbase + k * plane + static_cast<long long>(jr[s + 1]) * a.nx + ic] : 0.0;
     }
@@ -415,11 +433,14 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
 #pragma unroll
     for (int s = 0; s < JS + 2; ++s) up[s] = has_up ? *at(k + 1, s) : TU(0);
     const double czl = a.cz[3 * k], czd = a.cz[3 * k + 1], czu = a.cz[3 * k + 2];
+    const double xsk = CYL ? a.xscale[k] : 1.0;
 #pragma unroll
     for (int s = 0; s < JS; ++s) {
-      const double h = (dxy[s] + czd) * static_cast<double>(uc[s + 1]) + czl * static_cast<double>(um[s]) +
+      const double dd = CYL ? dxy[s] + czd + xsk * cxd : dxy[s] + czd;
+      const double xt = CYL ? xsk * xs[s] : xs[s];
+      const double h = dd * static_cast<double>(uc[s + 1]) + czl * static_cast<double>(um[s]) +
                        czu * static_cast<double>(up[s + 1]) + cyl[s] * static_cast<double>(uc[s]) +
-                       cyu[s] * static_cast<double>(uc[s + 2]) + xs[s];
+                       cyu[s] * static_cast<double>(uc[s + 2]) + xt;
       const double res = MODE == 1 ? fv[s] - h : h;
       if (iok && j0 + s < a.ny) out[rbase + k * plane + static_cast<long long>(j0 + s) * a.nx + i] = store_cvt<TOut>(res);
     }
@@ -442,6 +463,8 @@ hipError_t stencil_any(int mode, const TU* u, const double* f, void* out, Prec t
                        hipStream_t st) {
   const long long n = static_cast<long long>(a.nx) * a.ny * a.nz * a.nrhs;
   if (n == 0) return hipSuccess;
+  // the cylindrical operator is built for FP64 u and output only
+  if (a.xscale && (mode == 2 || !std::is_same<TU, double>::value || tout != P_F64)) return hipErrorInvalidValue;
   if (mode == 2) {
     const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
     if (tout == P_F64)
@@ -467,6 +490,13 @@ hipError_t stencil_any(int mode, const TU* u, const double* f, void* out, Prec t
   const dim3 grid(static_cast<unsigned>(tiles)), block(256);
   auto launch = [&](auto out_type, auto mode_c) {
     using TOut = decltype(out_type);
+    if constexpr (std::is_same<TU, double>::value && std::is_same<TOut, double>::value) {
+      if (a.xscale) {  // cylindrical plans: FP64 operator and residual only
+        hipLaunchKernelGGL((k_stencil<TOut, decltype(mode_c)::value, TU, true>), grid, block, 0, st, u, f,
+                           static_cast<TOut*>(out), a, zchunk, nzc, wx, nbx, nby);
+        return;
+      }
+    }
     hipLaunchKernelGGL((k_stencil<TOut, decltype(mode_c)::value, TU>), grid, block, 0, st, u, f,
                        static_cast<TOut*>(out), a, zchunk, nzc, wx, nbx, nby);
   };

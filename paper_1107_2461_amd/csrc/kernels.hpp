@@ -75,12 +75,16 @@ hipError_t mode_rot(const void* Msw, int K, const void* X, bool x_f64, void* Y, 
 // Batched Thomas solve along z (TPT, end of Section 3): for every RHS r and (b, a) line,
 // (K_z + c V_z) v = V_z g with c = lam_x[a] + lam_y[b] + sigma[r], in place on v (FP64).
 // The line (0, 0) is skipped when skip_null != 0.  chk: scratch of thomas_scratch_bytes.
+// Cylindrical plans (Section 6, eq. 44; x = theta, y = z, z = r): gdiag = dr / rc on the
+// radial axis, and the line (a, b) solves (K_r + lam_theta[a] G + (lam_z[b] + sigma) V_r) v =
+// V_r g with G = diag(gdiag) (NULL for Cartesian plans: G = V).
 struct ThomasArgs {
   const double* kdiag;   // K_z diagonal [nz]
   const double* koff;    // K_z off-diagonal [nz - 1]
   const double* vol;     // V_z [nz]
   const double* lamx;
   const double* lamy;
+  const double* gdiag = nullptr;
   int nx, ny, nz, nrhs;
   int skip_null;
   double sigma[kMaxRhs];
@@ -101,6 +105,11 @@ struct StencilArgs {
   const double* cy;   // [3 * ny]
   const double* cz;   // [3 * nz]
   int nx, ny, nz, nrhs;
+  // Cylindrical plans (x = theta, y = z, z = r): the x term of plane k is scaled by xscale[k]
+  // (1 / rc_k^2, the metric of eq. 41), and xper != 0 closes x periodically (cx's first lower
+  // and last upper entries couple to the other end).  xscale NULL: Cartesian.
+  const double* xscale = nullptr;
+  int xper = 0;
   double sigma[kMaxRhs];
   // optional: the first workgroup clears these words (the refinement norms of the sweep the
   // residual starts), so no launch of its own is needed

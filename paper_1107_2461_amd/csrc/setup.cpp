@@ -8,6 +8,33 @@
 
 namespace helm {
 
+namespace {
+
+// Rows of A = V^{-1} K from K and V (periodic axes also couple the first and last node).
+void fill_rows(Axis1D& ax) {
+  const int m = ax.m;
+  ax.lower.assign(m, 0.0);
+  ax.diag.assign(m, 0.0);
+  ax.upper.assign(m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    ax.diag[i] = ax.k_diag[i] / ax.vol[i];
+    if (i > 0) ax.lower[i] = ax.k_off[i - 1] / ax.vol[i];
+    if (i + 1 < m) ax.upper[i] = ax.k_off[i] / ax.vol[i];
+  }
+  if (ax.periodic) {
+    ax.lower[0] = ax.k_wrap / ax.vol[0];
+    ax.upper[m - 1] = ax.k_wrap / ax.vol[m - 1];
+  }
+}
+
+bool faces_ok(int n, const double* faces) {
+  for (int i = 0; i < n; ++i)
+    if (!(faces[i + 1] > faces[i]) || !std::isfinite(faces[i]) || !std::isfinite(faces[i + 1])) return false;
+  return true;
+}
+
+}  // namespace
+
 std::string build_operator_1d(int n, const double* faces, int loc, int bc_lo, int bc_hi, Axis1D& ax) {
   if (!faces) return "faces pointer is NULL";
   if (loc != 0 && loc != 1) return "loc must be HELM_CELL or HELM_FACE";
@@ -51,26 +78,140 @@ std::string build_operator_1d(int n, const double* faces, int loc, int bc_lo, in
   if (bc_lo == 0) ax.k_diag[0] += 1.0 / d_lo;
   if (bc_hi == 0) ax.k_diag[m - 1] += 1.0 / d_hi;
   ax.null_mode = (bc_lo == 1 && bc_hi == 1);
-  ax.lower.assign(m, 0.0);
-  ax.diag.assign(m, 0.0);
-  ax.upper.assign(m, 0.0);
-  for (int i = 0; i < m; ++i) {
-    ax.diag[i] = ax.k_diag[i] / ax.vol[i];
-    if (i > 0) ax.lower[i] = ax.k_off[i - 1] / ax.vol[i];
-    if (i + 1 < m) ax.upper[i] = ax.k_off[i] / ax.vol[i];
+  fill_rows(ax);
+  return "";
+}
+
+
+std::string build_operator_radial(int n, const double* faces, int bc_lo, int bc_hi, Axis1D& ax) {
+  if (!faces) return "faces pointer is NULL";
+  if ((bc_lo != 0 && bc_lo != 1) || (bc_hi != 0 && bc_hi != 1)) return "bad boundary code";
+  if (n < 2) return "too few cells on an axis";
+  if (!faces_ok(n, faces)) return "faces must be finite and strictly increasing";
+  if (!(faces[0] >= 0.0)) return "radial faces must start at r >= 0";
+  ax.faces.assign(faces, faces + n + 1);
+  ax.loc = 0;
+  const bool axis = faces[0] == 0.0;
+  ax.bc_lo = axis ? 1 : bc_lo;
+  ax.bc_hi = bc_hi;
+  ax.m = n;
+  std::vector<double> rc(n);
+  for (int i = 0; i < n; ++i) rc[i] = 0.5 * (faces[i] + faces[i + 1]);
+  ax.vol.resize(n);
+  ax.gdiag.resize(n);
+  ax.inv_r2.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const double dr = faces[i + 1] - faces[i];
+    ax.vol[i] = rc[i] * dr;
+    ax.gdiag[i] = dr / rc[i];
+    ax.inv_r2[i] = 1.0 / (rc[i] * rc[i]);
   }
+  ax.k_diag.assign(n, 0.0);
+  ax.k_off.assign(n - 1, 0.0);
+  for (int i = 0; i + 1 < n; ++i) {
+    const double g = faces[i + 1] / (rc[i + 1] - rc[i]);
+    ax.k_off[i] = -g;
+    ax.k_diag[i] += g;
+    ax.k_diag[i + 1] += g;
+  }
+  if (!axis && bc_lo == 0) ax.k_diag[0] += faces[0] / (rc[0] - faces[0]);
+  if (bc_hi == 0) ax.k_diag[n - 1] += faces[n] / (faces[n] - rc[n - 1]);
+  ax.null_mode = ax.bc_lo == 1 && bc_hi == 1;
+  fill_rows(ax);
+  return "";
+}
+
+std::string build_operator_periodic(int n, const double* faces, Axis1D& ax) {
+  if (!faces) return "faces pointer is NULL";
+  if (n < 3) return "a periodic axis needs at least three cells";
+  if (!faces_ok(n, faces)) return "faces must be finite and strictly increasing";
+  ax.faces.assign(faces, faces + n + 1);
+  ax.loc = 0;
+  ax.bc_lo = ax.bc_hi = 1;
+  ax.periodic = true;
+  ax.m = n;
+  std::vector<double> c(n);
+  for (int i = 0; i < n; ++i) c[i] = 0.5 * (faces[i] + faces[i + 1]);
+  ax.vol.resize(n);
+  for (int i = 0; i < n; ++i) ax.vol[i] = faces[i + 1] - faces[i];
+  ax.k_diag.assign(n, 0.0);
+  ax.k_off.assign(n - 1, 0.0);
+  for (int i = 0; i + 1 < n; ++i) {
+    const double g = 1.0 / (c[i + 1] - c[i]);
+    ax.k_off[i] = -g;
+    ax.k_diag[i] += g;
+    ax.k_diag[i + 1] += g;
+  }
+  const double gw = 1.0 / ((faces[n] - c[n - 1]) + (c[0] - faces[0]));
+  ax.k_wrap = -gw;
+  ax.k_diag[0] += gw;
+  ax.k_diag[n - 1] += gw;
+  ax.null_mode = true;  // no wall: the constant is in the null space
+  fill_rows(ax);
   return "";
 }
 
 namespace {
 
+// Householder reduction of a dense symmetric matrix A (m x m row-major) to tridiagonal form
+// T = Q^T A Q (Golub & Van Loan, Section 8.3.1): d, e receive the diagonal and off-diagonal of
+// T, Q (row-major) the accumulated orthogonal transform.
+template <typename R>
+void householder_tridiag(int m, std::vector<R> A, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Q) {
+  auto at = [&](int i, int j) -> R& { return A[static_cast<size_t>(i) * m + j]; };
+  Q.assign(static_cast<size_t>(m) * m, R(0));
+  for (int i = 0; i < m; ++i) Q[static_cast<size_t>(i) * m + i] = R(1);
+  std::vector<R> v(m), p(m), w(m);
+  for (int k = 0; k + 2 < m; ++k) {
+    // reflector H = I - 2 v v^T / (v^T v) mapping A[k+1.., k] onto a multiple of e_{k+1}
+    R alpha = 0;
+    for (int i = k + 1; i < m; ++i) alpha += at(i, k) * at(i, k);
+    alpha = std::sqrt(alpha);
+    if (alpha == R(0)) continue;
+    if (at(k + 1, k) > 0) alpha = -alpha;
+    std::fill(v.begin(), v.end(), R(0));
+    for (int i = k + 1; i < m; ++i) v[i] = at(i, k);
+    v[k + 1] -= alpha;
+    R vv = 0;
+    for (int i = k + 1; i < m; ++i) vv += v[i] * v[i];
+    if (vv == R(0)) continue;
+    const R beta = R(2) / vv;
+    // A <- H A H on the trailing block: p = beta A v, w = p - (beta/2)(v^T p) v, A -= v w^T + w v^T
+    for (int i = k; i < m; ++i) {
+      R s = 0;
+      for (int j = k + 1; j < m; ++j) s += at(i, j) * v[j];
+      p[i] = beta * s;
+    }
+    R vp = 0;
+    for (int i = k + 1; i < m; ++i) vp += v[i] * p[i];
+    for (int i = k; i < m; ++i) w[i] = p[i] - R(0.5) * beta * vp * v[i];
+    for (int i = k; i < m; ++i)
+      for (int j = k; j < m; ++j) at(i, j) -= v[i] * w[j] + w[i] * v[j];
+    // Q <- Q H
+    for (int r = 0; r < m; ++r) {
+      R s = 0;
+      for (int j = k + 1; j < m; ++j) s += Q[static_cast<size_t>(r) * m + j] * v[j];
+      s *= beta;
+      for (int j = k + 1; j < m; ++j) Q[static_cast<size_t>(r) * m + j] -= s * v[j];
+    }
+  }
+  d.resize(m);
+  e.assign(m, R(0));
+  for (int i = 0; i < m; ++i) d[i] = at(i, i);
+  for (int i = 0; i + 1 < m; ++i) e[i] = at(i + 1, i);
+}
+
 // Implicit QL with shifts on a symmetric tridiagonal matrix (d: diagonal, e: off-diagonal,
 // e[i] couples i and i + 1), accumulating the rotations into Z (row-major, Z[k][a] =
 // component k of vector a).  On return d holds the eigenvalues in ascending order.
+// keep_z: Z holds an orthogonal basis on entry (a Householder transform) and the rotations
+// are applied to it, so the columns become eigenvectors of the matrix that was reduced.
 template <typename R>
-bool tridiag_ql(int m, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Z) {
-  Z.assign(static_cast<size_t>(m) * m, R(0));
-  for (int i = 0; i < m; ++i) Z[static_cast<size_t>(i) * m + i] = R(1);
+bool tridiag_ql(int m, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Z, bool keep_z = false) {
+  if (!keep_z) {
+    Z.assign(static_cast<size_t>(m) * m, R(0));
+    for (int i = 0; i < m; ++i) Z[static_cast<size_t>(i) * m + i] = R(1);
+  }
   e.resize(m);
   e[m - 1] = R(0);
   const R eps = std::numeric_limits<R>::epsilon();
@@ -157,10 +298,23 @@ std::string eigen_1d(Axis1D& ax) {
   for (int i = 0; i < m; ++i) sv[i] = std::sqrt(static_cast<R>(ax.vol[i]));
   for (int i = 0; i < m; ++i) d[i] = static_cast<R>(ax.k_diag[i]) / static_cast<R>(ax.vol[i]);
   for (int i = 0; i + 1 < m; ++i) e[i] = static_cast<R>(ax.k_off[i]) / (sv[i] * sv[i + 1]);
-  if (!tridiag_ql<R>(m, d, e, Q)) return "tridiagonal eigensolver did not converge";
-  // Neumann at both walls: the constant is an exact null vector of K, so the smallest
-  // eigenpair is set exactly: lambda_0 = 0, q_0 = V^{1/2} 1 / ||V^{1/2} 1||; the other
-  // vectors are re-orthogonalized against it.
+  if (ax.periodic) {
+    // V^{-1/2} K V^{-1/2} is cyclic: reduce the dense symmetric matrix to tridiagonal form first
+    std::vector<R> T(static_cast<size_t>(m) * m, R(0));
+    for (int i = 0; i < m; ++i) T[static_cast<size_t>(i) * m + i] = d[i];
+    for (int i = 0; i + 1 < m; ++i)
+      T[static_cast<size_t>(i) * m + i + 1] = T[static_cast<size_t>(i + 1) * m + i] = e[i];
+    const R w = static_cast<R>(ax.k_wrap) / (sv[0] * sv[m - 1]);
+    T[static_cast<size_t>(m - 1)] += w;
+    T[static_cast<size_t>(m - 1) * m] += w;
+    householder_tridiag<R>(m, T, d, e, Q);
+    if (!tridiag_ql<R>(m, d, e, Q, true)) return "tridiagonal eigensolver did not converge";
+  } else if (!tridiag_ql<R>(m, d, e, Q)) {
+    return "tridiagonal eigensolver did not converge";
+  }
+  // Neumann at both walls (or no wall, periodic): the constant is an exact null vector of K,
+  // so the smallest eigenpair is set exactly: lambda_0 = 0, q_0 = V^{1/2} 1 / ||V^{1/2} 1||;
+  // the other vectors are re-orthogonalized against it.
   if (ax.null_mode) {
     R nrm = 0;
     for (int i = 0; i < m; ++i) nrm += static_cast<R>(ax.vol[i]);

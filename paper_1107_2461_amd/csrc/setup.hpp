@@ -26,7 +26,13 @@ struct Axis1D {
   std::vector<double> lower, diag, upper;  // rows of A = V^{-1} K
   std::vector<double> lam;         // eigenvalues, ascending, m
   std::vector<double> E, Einv;     // m x m row-major: E[i*m + a] = component i of vector a
-  bool null_mode = false;          // Neumann at both ends: lambda_0 = 0 exactly
+  bool null_mode = false;          // Neumann at both ends (or periodic): lambda_0 = 0 exactly
+  // Cylindrical axes (Section 6, eq. 41).
+  bool periodic = false;           // theta axis closed on itself: node m-1 couples to node 0
+  double k_wrap = 0.0;             // K entry of that coupling (negative)
+  std::vector<double> gdiag;       // radial axis: dr_i / rc_i, the metric weight of the theta
+                                   // term in the K form (its V^{-1} form is 1 / rc_i^2)
+  std::vector<double> inv_r2;      // radial axis: 1 / rc_i^2
 };
 
 // Builds the 1D operator; returns an empty string on success, else a message.
@@ -39,7 +45,21 @@ std::string build_operator_1d(int n, const double* faces, int loc, int bc_lo, in
 // columns.  Returns false if an eigenvalue failed to converge.
 bool tridiag_eigen(int m, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Z);
 
-// Eigen-decomposition of an operator built by build_operator_1d (fills lam, E, Einv).
+// Eigen-decomposition of an operator built by one of the builders here (fills lam, E, Einv).
+// A periodic axis (a cyclic tridiagonal K) is reduced to tridiagonal form by Householder
+// reflections before the QL iteration.
 std::string eigen_1d(Axis1D& ax);
+
+// Radial axis of the cylindrical operator (Section 6, eq. 41, the D_rr part): cells
+// [r_i, r_{i+1}] with midpoints rc_i, r_0 >= 0.  K has link conductance r_{i+1} / (rc_{i+1} -
+// rc_i) (face area per unit angle and height over the node distance), a Dirichlet wall adds
+// r_wall / (distance to the wall), an axis (r_0 = 0, zero area) and a Neumann wall nothing;
+// V = rc_i (r_{i+1} - r_i).  Also fills gdiag and inv_r2.  bc_lo is ignored when r_0 = 0.
+std::string build_operator_radial(int n, const double* faces, int bc_lo, int bc_hi, Axis1D& ax);
+
+// Periodic axis (the cylindrical theta direction closed on itself): cell-centred nodes, the
+// last cell's upper face is the first cell's lower face, so node n-1 couples to node 0 across
+// the distance (t_n - tc_{n-1}) + (tc_0 - t_0).  n >= 3.
+std::string build_operator_periodic(int n, const double* faces, Axis1D& ax);
 
 }  // namespace helm

@@ -73,9 +73,21 @@ struct DevAxis {
   double* vol = nullptr;     // m
   double* E = nullptr;       // m*m row-major
   double* Einv = nullptr;    // m*m row-major
+  double* gdiag = nullptr;   // radial axis: dr / rc (Thomas metric term)
+  double* inv_r2 = nullptr;  // radial axis: 1 / rc^2 (stencil metric)
   void* sw[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][fwd, inv]
   void* sw3[2] = {nullptr, nullptr};  // split-BF16 pieces [fwd, inv]
 };
+
+// How an axis' 1D operator is built: Cartesian (eq. 23), or the radial and periodic-theta
+// axes of the cylindrical operator (Section 6, eq. 41).
+enum AxisKind : int { AXIS_CART = 0, AXIS_RADIAL = 1, AXIS_PERIODIC = 2 };
+
+std::string build_axis(int kind, int n, const double* faces, int loc, int lo, int hi, Axis1D& h) {
+  if (kind == AXIS_RADIAL) return build_operator_radial(n, faces, lo, hi, h);
+  if (kind == AXIS_PERIODIC) return build_operator_periodic(n, faces, h);
+  return build_operator_1d(n, faces, loc, lo, hi, h);
+}
 
 std::mutex g_cache_mu;
 std::map<std::string, std::weak_ptr<DevAxis>> g_cache;
@@ -92,8 +104,9 @@ helm_status from_hip(hipError_t e) {
   return HELM_EDEVICE;
 }
 
-std::string axis_key(int n, const double* faces, int loc, int lo, int hi, int device, const DevAlloc& al) {
+std::string axis_key(int kind, int n, const double* faces, int loc, int lo, int hi, int device, const DevAlloc& al) {
   std::string k(reinterpret_cast<const char*>(faces), sizeof(double) * (n + 1));
+  k.push_back(static_cast<char>(kind));
   k.push_back(static_cast<char>(loc));
   k.push_back(static_cast<char>(lo));
   k.push_back(static_cast<char>(hi));
@@ -102,11 +115,11 @@ std::string axis_key(int n, const double* faces, int loc, int lo, int hi, int de
   return k;
 }
 
-helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, const DevAlloc& al,
+helm_status get_axis(int kind, int n, const double* faces, int loc, int lo, int hi, const DevAlloc& al,
                      std::shared_ptr<DevAxis>& out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
-  const std::string key = axis_key(n, faces, loc, lo, hi, dev, al);
+  const std::string key = axis_key(kind, n, faces, loc, lo, hi, dev, al);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
@@ -121,7 +134,7 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, const 
   ax->mem.alloc = al;
   ax->mem.device = dev;
   Axis1D& h = ax->host;
-  if (!build_operator_1d(n, faces, loc, lo, hi, h).empty()) return HELM_EINVAL;
+  if (!build_axis(kind, n, faces, loc, lo, hi, h).empty()) return HELM_EINVAL;
   if (h.m > 512) return HELM_EINVAL;
   if (!eigen_1d(h).empty()) return HELM_EINVAL;
   const int m = h.m;
@@ -140,6 +153,8 @@ helm_status get_axis(int n, const double* faces, int loc, int lo, int hi, const 
   if (e == hipSuccess) e = mem.upload(&ax->vol, h.vol.data(), m);
   if (e == hipSuccess) e = mem.upload(&ax->E, h.E.data(), h.E.size());
   if (e == hipSuccess) e = mem.upload(&ax->Einv, h.Einv.data(), h.Einv.size());
+  if (e == hipSuccess && !h.gdiag.empty()) e = mem.upload(&ax->gdiag, h.gdiag.data(), h.gdiag.size());
+  if (e == hipSuccess && !h.inv_r2.empty()) e = mem.upload(&ax->inv_r2, h.inv_r2.data(), h.inv_r2.size());
   for (int p = 0; p < 3 && e == hipSuccess; ++p) {
     const Prec pr = static_cast<Prec>(p);
     const size_t bytes = swizzled_bytes(pr, m);
@@ -304,6 +319,7 @@ struct helm_plan {
   double sigma = 0.0;
   helm_opts opts{};
   bool all_neumann = false;
+  bool cyl = false;       // cylindrical operator (x = theta, y = z, z = r): FP64, Thomas along r
   int device = 0;
   std::shared_ptr<DevBuf> lamxy;             // m[0] * m[1]: lamx[a] + lamy[b] (split-BF16), shared
   mutable StageProfiler prof;
@@ -418,8 +434,8 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
   bool alln = true;
   for (int d = 0; d < 3; ++d) {
     if (!grid->faces[d]) return HELM_EINVAL;
-    const helm_status s =
-        get_axis(grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d], DevAlloc::from(o), p->ax[d]);
+    const helm_status s = get_axis(AXIS_CART, grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d],
+                                   DevAlloc::from(o), p->ax[d]);
     if (s != HELM_OK) return s;
     p->m[d] = p->ax[d]->host.m;
     alln = alln && p->ax[d]->host.null_mode;
@@ -431,6 +447,74 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
     if (s != HELM_OK) return s;
   }
   *out = p.release();
+  return HELM_OK;
+}
+
+helm_status helm_cyl_setup(const helm_cyl_grid* grid, const helm_bc* bc, double sigma, const helm_opts* opts,
+                           helm_plan** out) {
+  if (!grid || !bc || !out) return HELM_EINVAL;
+  *out = nullptr;
+  if (!std::isfinite(sigma) || sigma < 0.0) return HELM_EINVAL;
+  helm_opts o;
+  helm_default_opts(&o);
+  if (opts) o = *opts;
+  o.method = HELM_TPT_Z;  // eq. 44: transforms in theta and z, one Thomas solve per radial line
+  if (o.precision != HELM_FP64 || !valid_opts(o)) return HELM_EINVAL;
+  if (grid->theta_periodic != 0 && grid->theta_periodic != 1) return HELM_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!grid->faces[d]) return HELM_EINVAL;
+  std::unique_ptr<helm_plan> p(new (std::nothrow) helm_plan());
+  if (!p) return HELM_ENOMEM;
+  p->opts = o;
+  p->sigma = sigma;
+  p->cyl = true;
+  if (hipGetDevice(&p->device) != hipSuccess) return HELM_EDEVICE;
+  const DevAlloc al = DevAlloc::from(o);
+  // plan axes: x = theta (fastest), y = z, z = r (slowest: the Thomas direction)
+  helm_status s = grid->theta_periodic
+                      ? get_axis(AXIS_PERIODIC, grid->n[1], grid->faces[1], HELM_CELL, 1, 1, al, p->ax[0])
+                      : get_axis(AXIS_CART, grid->n[1], grid->faces[1], HELM_CELL, bc->lo[1], bc->hi[1], al, p->ax[0]);
+  if (s != HELM_OK) return s;
+  if ((s = get_axis(AXIS_CART, grid->n[2], grid->faces[2], HELM_CELL, bc->lo[2], bc->hi[2], al, p->ax[1])) != HELM_OK)
+    return s;
+  if ((s = get_axis(AXIS_RADIAL, grid->n[0], grid->faces[0], HELM_CELL, bc->lo[0], bc->hi[0], al, p->ax[2])) !=
+      HELM_OK)
+    return s;
+  bool alln = true;
+  for (int d = 0; d < 3; ++d) {
+    p->m[d] = p->ax[d]->host.m;
+    alln = alln && p->ax[d]->host.null_mode;
+  }
+  p->all_neumann = alln;
+  *out = p.release();
+  return HELM_OK;
+}
+
+helm_status helm_host_operator_cyl(int kind, int n, const double* faces, int bc_lo, int bc_hi, int* m_out,
+                                   double* lower, double* diag, double* upper, double* vol) {
+  if (kind != 0 && kind != 1) return HELM_EINVAL;
+  Axis1D ax;
+  if (!build_axis(kind == 0 ? AXIS_RADIAL : AXIS_PERIODIC, n, faces, HELM_CELL, bc_lo, bc_hi, ax).empty())
+    return HELM_EINVAL;
+  if (m_out) *m_out = ax.m;
+  if (lower) std::copy(ax.lower.begin(), ax.lower.end(), lower);
+  if (diag) std::copy(ax.diag.begin(), ax.diag.end(), diag);
+  if (upper) std::copy(ax.upper.begin(), ax.upper.end(), upper);
+  if (vol) std::copy(ax.vol.begin(), ax.vol.end(), vol);
+  return HELM_OK;
+}
+
+helm_status helm_host_eigen_cyl(int kind, int n, const double* faces, int bc_lo, int bc_hi, int* m_out, double* lam,
+                                double* E, double* Einv) {
+  if (kind != 0 && kind != 1) return HELM_EINVAL;
+  Axis1D ax;
+  if (!build_axis(kind == 0 ? AXIS_RADIAL : AXIS_PERIODIC, n, faces, HELM_CELL, bc_lo, bc_hi, ax).empty())
+    return HELM_EINVAL;
+  if (!eigen_1d(ax).empty()) return HELM_EINVAL;
+  if (m_out) *m_out = ax.m;
+  if (lam) std::copy(ax.lam.begin(), ax.lam.end(), lam);
+  if (E) std::copy(ax.E.begin(), ax.E.end(), E);
+  if (Einv) std::copy(ax.Einv.begin(), ax.Einv.end(), Einv);
   return HELM_OK;
 }
 
@@ -624,6 +708,8 @@ StencilArgs stencil_args(const helm_plan* p, int nrhs, const double* sig) {
   a.ny = p->m[1];
   a.nz = p->m[2];
   a.nrhs = nrhs;
+  a.xscale = p->cyl ? p->ax[2]->inv_r2 : nullptr;
+  a.xper = p->ax[0]->host.periodic ? 1 : 0;
   for (int r = 0; r < nrhs; ++r) a.sigma[r] = sig[r];
   return a;
 }
@@ -667,7 +753,8 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
   for (int r = 0; r < nrhs; ++r) {
     sig[r] = sigma_per_rhs ? sigma_per_rhs[r] : p->sigma;
     if (!std::isfinite(sig[r])) return HELM_EINVAL;
-    if (sig[r] != p->sigma && has_zero_denominator(p, sig[r])) return HELM_ESINGULAR;
+    if (p->cyl && sig[r] < 0.0) return HELM_EINVAL;
+    if (!p->cyl && sig[r] != p->sigma && has_zero_denominator(p, sig[r])) return HELM_ESINGULAR;
   }
   DeviceGuard dg(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -710,7 +797,7 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
     const DevAxis& Y = *p->ax[1];
     const DevAxis& Z = *p->ax[2];
     const long long nx = p->m[0], ny = p->m[1], nz = p->m[2];
-    if (p->opts.method == HELM_TPF) {
+    if (p->opts.method == HELM_TPF && !p->cyl) {
       // f -> W -> u -> W -> u -> W -> u  (u may alias f: f is consumed by the first product)
       e = tpf_products(p, P_F64, f, W, u, u, EPI_STORE, nrhs, sig, nullptr, 0, st);
     } else {
@@ -722,6 +809,7 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
       ta.vol = Z.vol;
       ta.lamx = X.lam;
       ta.lamy = Y.lam;
+      ta.gdiag = p->cyl ? Z.gdiag : nullptr;  // eq. 44: the theta eigenvalue enters through 1 / r^2
       ta.nx = static_cast<int>(nx);
       ta.ny = static_cast<int>(ny);
       ta.nz = static_cast<int>(nz);

@@ -114,3 +114,83 @@ def test_host_argument_validation():
     assert lib.helm_host_operator_1d(2, nanf.ctypes.data_as(L.DP), 0, 0, 0, C.byref(m), None, None, None,
                                      None) == L.HELM_EINVAL
     assert lib.helm_setup(None, None, 0.0, None, None) == L.HELM_EINVAL
+
+
+# ------------------------------------------------------------------ cylindrical axes (Section 6)
+
+def _dense_rows(lower, diag, upper, periodic=False):
+    m = len(diag)
+    A = np.diag(diag) + np.diag(lower[1:], -1) + np.diag(upper[:-1], 1)
+    if periodic:
+        A[0, m - 1] += lower[0]
+        A[m - 1, 0] += upper[m - 1]
+    return A
+
+
+@pytest.mark.parametrize("r0,lo,hi", [(0.0, fv.NEUMANN, fv.DIRICHLET), (0.3, fv.DIRICHLET, fv.NEUMANN),
+                                      (0.3, fv.NEUMANN, fv.NEUMANN)])
+def test_host_radial_operator_matches_oracle(r0, lo, hi):
+    """The library's radial operator equals the oracle's cylindrical assembly on an (n_r, 1, 1)
+    sector whose theta and z walls are Neumann (no theta or z coupling remains)."""
+    from oracle import cyl
+    from paper_1107_2461_amd import host_operator_cyl
+    rf = workloads.stretched_faces(11, 1.5, r0, 1.4)
+    lower, diag, upper, vol = host_operator_cyl(0, rf, lo, hi)
+    K3, v3, _ = cyl.assemble(rf, [0.0, 0.7], [0.0, 0.4], (lo, hi), (fv.NEUMANN, fv.NEUMANN),
+                             (fv.NEUMANN, fv.NEUMANN))
+    A = K3.toarray() / v3[:, None]
+    assert np.abs(_dense_rows(lower, diag, upper) - A).max() <= 1e-13 * np.abs(A).max()
+    np.testing.assert_allclose(vol * 0.7 * 0.4, v3, rtol=1e-14)
+
+
+def test_host_periodic_operator_matches_oracle():
+    """The library's periodic theta operator times 1 / rc^2 equals the oracle's assembly on a
+    one-cell annulus [1, 2] (Neumann radial and axial walls)."""
+    from oracle import cyl
+    from paper_1107_2461_amd import host_operator_cyl
+    tf = workloads.stretched_faces(13, 1.25, 0.0, 2 * np.pi)
+    lower, diag, upper, vol = host_operator_cyl(1, tf)
+    K3, v3, _ = cyl.assemble([1.0, 2.0], tf, [0.0, 0.5], (fv.NEUMANN, fv.NEUMANN), None, (fv.NEUMANN, fv.NEUMANN))
+    A = K3.toarray() / v3[:, None]
+    assert np.abs(_dense_rows(lower, diag, upper, periodic=True) / 1.5**2 - A).max() <= 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("M", [3, 8, 13])
+def test_host_periodic_eigen(M):
+    """Uniform periodic axis: eigenvalues (4 / h^2) sin^2(pi m / M), m = 0..M-1 (pairs m, M - m
+    coincide); A E = E diag(lam), Einv E = I, lam_0 = 0 exactly.  Stretched: the same invariants
+    and the eigenvalues of the dense matrix by scipy."""
+    from paper_1107_2461_amd import host_eigen_cyl, host_operator_cyl
+    for tf in (np.linspace(0.0, 2 * np.pi, M + 1), workloads.stretched_faces(M, 1.5, 0.0, 2 * np.pi)):
+        lam, E, Ei = host_eigen_cyl(1, tf)
+        lower, diag, upper, vol = host_operator_cyl(1, tf)
+        A = _dense_rows(lower, diag, upper, periodic=True)
+        assert lam[0] == 0.0
+        assert np.abs(A @ E - E * lam[None, :]).max() <= 1e-12 * np.abs(A).max()
+        assert np.abs(Ei @ E - np.eye(M)).max() <= 1e-12
+        ref = np.sort(np.linalg.eigvals(A).real)
+        assert np.abs(np.sort(lam) - ref).max() <= 1e-11 * np.abs(A).max()
+    h = 2 * np.pi / M
+    lam, _, _ = host_eigen_cyl(1, np.linspace(0.0, 2 * np.pi, M + 1))
+    closed = np.sort(4 / h**2 * np.sin(np.pi * np.arange(M) / M) ** 2)
+    assert np.abs(lam - closed).max() <= 1e-12 * closed.max()
+
+
+def test_host_radial_eigen_generalized():
+    from paper_1107_2461_amd import host_eigen_cyl, host_operator_cyl
+    rf = workloads.stretched_faces(20, 1.5, 0.0, 1.0)
+    lam, E, Ei = host_eigen_cyl(0, rf, fv.NEUMANN, fv.NEUMANN)
+    A = _dense_rows(*host_operator_cyl(0, rf, fv.NEUMANN, fv.NEUMANN)[:3])
+    assert lam[0] == 0.0 and lam[1] > 0
+    assert np.abs(A @ E - E * lam[None, :]).max() <= 1e-11 * np.abs(A).max()
+    assert np.abs(Ei @ E - np.eye(20)).max() <= 1e-12
+
+
+def test_host_cyl_refusals():
+    from paper_1107_2461_amd import HelmError, host_operator_cyl
+    with pytest.raises(HelmError, match="EINVAL"):
+        host_operator_cyl(0, [-0.1, 0.5, 1.0])          # negative radius
+    with pytest.raises(HelmError, match="EINVAL"):
+        host_operator_cyl(1, [0.0, 1.0, 2.0])           # periodic axis with two cells
+    with pytest.raises(HelmError, match="EINVAL"):
+        host_operator_cyl(2, [0.0, 1.0, 2.0, 3.0])      # unknown kind
