@@ -57,8 +57,13 @@ enum {
   HELM_BF16X3 = 5, HELM_BF16X3_IR = 6
 };
 /* TPF: eigen-transforms along x, y, z (eq. 29).  TPT_Z: eigen-transforms along x, y and
- * one Thomas tridiagonal solve per z line (end of Section 3). */
-enum { HELM_TPF = 0, HELM_TPT_Z = 1 };
+ * one Thomas tridiagonal solve per z line (end of Section 3).  FFT: TPF in which every
+ * uniform axis whose walls give a sine or cosine eigenbasis (cell-centred: any wall pair;
+ * face-located: both Dirichlet or both Neumann) and whose transform length 2M has no prime
+ * factor above 7 (M <= 512) is transformed by a fast sine/cosine transform in O(N log N)
+ * instead of the N x N eigenvector product (the fast-solver route the paper names for
+ * uniform grids, Sections 1 and 3); other axes keep the product.  FP64 only. */
+enum { HELM_TPF = 0, HELM_TPT_Z = 1, HELM_FFT = 2 };
 /* All-Neumann Laplace null mode (eq. 28 discussion): PROJECT sets the zero mode of the
  * solution to 0 (the right-hand side is projected onto the range and u has zero
  * volume-weighted mean); PAPER_EQ28 replaces the zero denominator by 1 as in eq. 28. */
@@ -88,7 +93,7 @@ typedef void (*helm_free_fn)(void* ptr, size_t bytes, void* ctx);
 
 typedef struct {
   int precision;            /* HELM_FP64 (default) ... HELM_BF16X3_IR */
-  int method;               /* HELM_TPF (default) or HELM_TPT_Z */
+  int method;               /* HELM_TPF (default), HELM_TPT_Z or HELM_FFT (FP64 only) */
   double ir_tol;            /* refinement stops when the correction max|du| / max|u| of a sweep, or
                                its product with the observed contraction factor (the predicted
                                next correction, when that factor is below 1/2), is <= ir_tol
@@ -165,6 +170,10 @@ helm_status helm_solve(helm_plan* plan, const double* f, double* u, int nrhs,
 #define HELM_NOALLOC_MAX_WORKSPACE ((size_t)256 << 20)
 helm_status helm_solve_noalloc(helm_plan* plan, const double* f, double* u, int nrhs,
                                const double* sigma_per_rhs, void* stream, helm_info* info);
+
+/* Bit d of *mask is set when axis d of the plan is transformed by the fast sine/cosine
+ * transform (HELM_FFT plans with a uniform axis of a supported kind); 0 for other plans. */
+helm_status helm_fast_axes(const helm_plan* plan, int* mask);
 
 /* Hu = (sigma I - Lap_h) u with the FP64 7-point operator (the Kronecker sum of eq. 29),
  * device pointers [nrhs][nz][ny][nx]; asynchronous.  Hu must not alias u. */

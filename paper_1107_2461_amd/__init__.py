@@ -273,6 +273,12 @@ class Plan:
         check(load().helm_profile_read(self._h, ms, n), "helm_profile_read")
         return {name: (ms[i], n[i]) for i, name in enumerate(_lib.STAGES) if n[i]}
 
+    def fast_axes(self):
+        """Axes (0 = x, 1 = y, 2 = z) transformed by the fast sine/cosine transform (helm_fast_axes)."""
+        m = C.c_int()
+        check(load().helm_fast_axes(self._h, C.byref(m)), "helm_fast_axes")
+        return tuple(d for d in range(3) if (m.value >> d) & 1)
+
     def eigen(self, axis):
         lib = load()
         n = C.c_int()

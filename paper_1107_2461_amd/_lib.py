@@ -12,14 +12,14 @@ HELM_OK, HELM_EINVAL, HELM_ESINGULAR, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOTCONVER
 DIRICHLET, NEUMANN = 0, 1
 CELL, FACE = 0, 1
 FP64, FP32, BF16, FP32_IR, BF16_IR, BF16X3, BF16X3_IR = range(7)
-TPF, TPT_Z = 0, 1
+TPF, TPT_Z, FFT = 0, 1, 2
 NULL_PROJECT, NULL_PAPER_EQ28 = 0, 1
 STAGES = ("x_fwd", "y_fwd", "z_fwd_div", "z_inv", "y_inv", "x_inv", "thomas", "null_line", "residual", "convert",
           "apply", "other", "update", "x_fwd_rhs", "z_inv_u")
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp32_ir": FP32_IR, "bf16_ir": BF16_IR, "bf16x3": BF16X3,
               "bf16x3_ir": BF16X3_IR}
-METHODS = {"tpf": TPF, "tpt": TPT_Z}
+METHODS = {"tpf": TPF, "tpt": TPT_Z, "fft": FFT}
 
 
 class HelmGrid(C.Structure):
@@ -74,6 +74,7 @@ SIGNATURES = {
     "helm_solve": (C.c_int, [P, P, P, C.c_int, DP, P, P, C.POINTER(HelmInfo)]),
     "helm_solve_noalloc": (C.c_int, [P, P, P, C.c_int, DP, P, C.POINTER(HelmInfo)]),
     "helm_apply": (C.c_int, [P, P, P, C.c_int, DP, P]),
+    "helm_fast_axes": (C.c_int, [P, IP]),
     "helm_get_eigen": (C.c_int, [P, C.c_int, IP, DP, DP, DP]),
     "helm_destroy": (None, [P]),
     "helm_pressure_setup": (C.c_int, [C.POINTER(HelmGrid), C.POINTER(HelmOpts), C.POINTER(P)]),

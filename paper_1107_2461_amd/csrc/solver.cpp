@@ -22,6 +22,7 @@
 
 #include "../../include/helm.h"
 #include "alloc.hpp"
+#include "fft.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 #include "solve_impl.hpp"
@@ -75,6 +76,8 @@ struct DevAxis {
   double* Einv = nullptr;    // m*m row-major
   double* gdiag = nullptr;   // radial axis: dr / rc (Thomas metric term)
   double* inv_r2 = nullptr;  // radial axis: 1 / rc^2 (stencil metric)
+  bool fft_ok = false;       // uniform axis with a fast sine/cosine transform (HELM_FFT)
+  FftTables fft[2];          // [forward (E^{-1}), inverse (E)]
   void* sw[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][fwd, inv]
   void* sw3[2] = {nullptr, nullptr};  // split-BF16 pieces [fwd, inv]
 };
@@ -153,6 +156,37 @@ helm_status get_axis(int kind, int n, const double* faces, int loc, int lo, int 
   if (e == hipSuccess) e = mem.upload(&ax->vol, h.vol.data(), m);
   if (e == hipSuccess) e = mem.upload(&ax->E, h.E.data(), h.E.size());
   if (e == hipSuccess) e = mem.upload(&ax->Einv, h.Einv.data(), h.Einv.size());
+  if (e == hipSuccess) {  // fast transform tables of a uniform axis
+    int sine = 0, M = 0;
+    double alpha = 0.0, beta = 0.0;
+    FftHost hf, hi;
+    if (fft_axis_params(h, sine, alpha, beta, M) && fft_plan(sine, alpha, beta, M, m, true, hf) &&
+        fft_plan(sine, alpha, beta, M, m, false, hi)) {
+      double* W = nullptr;
+      double* pf[2] = {nullptr, nullptr};
+      double* pi[2] = {nullptr, nullptr};
+      e = mem.upload(&W, hf.W.data(), hf.W.size());
+      if (e == hipSuccess) e = mem.upload(&pf[0], hf.pre.data(), hf.pre.size());
+      if (e == hipSuccess) e = mem.upload(&pf[1], hf.post.data(), hf.post.size());
+      if (e == hipSuccess) e = mem.upload(&pi[0], hi.pre.data(), hi.pre.size());
+      if (e == hipSuccess) e = mem.upload(&pi[1], hi.post.data(), hi.post.size());
+      const FftHost* hs[2] = {&hf, &hi};
+      double* const* ps[2] = {pf, pi};
+      for (int dir = 0; dir < 2; ++dir) {
+        FftTables& t = ax->fft[dir];
+        t.L = hs[dir]->L;
+        t.N = hs[dir]->N;
+        t.M = hs[dir]->M;
+        t.nst = hs[dir]->nst;
+        t.lines = hs[dir]->lines;
+        for (int q = 0; q < t.nst; ++q) t.rad[q] = hs[dir]->rad[q];
+        t.W = W;
+        t.pre = ps[dir][0];
+        t.post = ps[dir][1];
+      }
+      ax->fft_ok = e == hipSuccess;
+    }
+  }
   if (e == hipSuccess && !h.gdiag.empty()) e = mem.upload(&ax->gdiag, h.gdiag.data(), h.gdiag.size());
   if (e == hipSuccess && !h.inv_r2.empty()) e = mem.upload(&ax->inv_r2, h.inv_r2.data(), h.inv_r2.size());
   for (int p = 0; p < 3 && e == hipSuccess; ++p) {
@@ -324,6 +358,9 @@ struct helm_plan {
   std::shared_ptr<DevBuf> lamxy;             // m[0] * m[1]: lamx[a] + lamy[b] (split-BF16), shared
   mutable StageProfiler prof;
   long long npts() const { return static_cast<long long>(m[0]) * m[1] * m[2]; }
+  // The Thomas form (FP64): TPT_Z plans and every cylindrical plan.  The workspace layout and the
+  // solve dispatch both use this, so a Thomas solve always has its checkpoint region.
+  bool thomas() const { return cyl || opts.method == HELM_TPT_Z; }
   bool refined() const {
     return opts.precision == HELM_FP32_IR || opts.precision == HELM_BF16_IR || opts.precision == HELM_BF16X3_IR;
   }
@@ -393,12 +430,12 @@ helm_status helm_host_eigen_1d(int n, const double* faces, int loc, int bc_lo, i
 
 static bool valid_opts(const helm_opts& o) {
   if (o.precision < HELM_FP64 || o.precision > HELM_BF16X3_IR) return false;
-  if (o.method != HELM_TPF && o.method != HELM_TPT_Z) return false;
+  if (o.method != HELM_TPF && o.method != HELM_TPT_Z && o.method != HELM_FFT) return false;
   if (o.null_mode != HELM_NULL_PROJECT && o.null_mode != HELM_NULL_PAPER_EQ28) return false;
   if (!(o.ir_tol >= 0.0) || o.max_sweeps < 1) return false;
   if (!DevAlloc::from(o).valid()) return false;
-  // The Thomas path runs in FP64 only.
-  if (o.method == HELM_TPT_Z && o.precision != HELM_FP64) return false;
+  // The Thomas and fast-transform paths run in FP64 only.
+  if ((o.method == HELM_TPT_Z || o.method == HELM_FFT) && o.precision != HELM_FP64) return false;
   return true;
 }
 
@@ -530,7 +567,7 @@ static void workspace_layout(const helm_plan* p, int nrhs, size_t* total, size_t
     *off_a = 0;
     t = align_up(P * 8, 256);
     *off_b = t;
-    if (p->opts.method == HELM_TPT_Z) t += align_up(thomas_scratch_bytes(p->m[0], p->m[1], p->m[2], nrhs), 256);
+    if (p->thomas()) t += align_up(thomas_scratch_bytes(p->m[0], p->m[1], p->m[2], nrhs), 256);
     *off_norms = t;
   } else {
     const size_t es = p->prec() == P_BF16 ? 2 : 4;
@@ -671,30 +708,63 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
     });
   }
   const int ip = static_cast<int>(pr);
+  // HELM_FFT (FP64): uniform axes by fast sine/cosine transforms, the rest by the products
+  const bool fast = pr == P_F64 && p->opts.method == HELM_FFT;
+  const bool fx = fast && X.fft_ok, fy = fast && Y.fft_ok, fz = fast && Z.fft_ok;
+  const long long P3 = nx * ny * nz;
+  FftLines lx, ly, lz;  // lines along x (contiguous), y and z (strided) of all right-hand sides
+  lx.nlines = nrhs * nz * ny;
+  lx.n0 = ny;
+  lx.n1 = nz;
+  lx.t0 = nx;
+  lx.t1 = nx * ny;
+  lx.t2 = P3;
+  lx.se = 1;
+  ly.nlines = nrhs * nz * nx;
+  ly.n0 = nx;
+  ly.n1 = nz;
+  ly.t0 = 1;
+  ly.t1 = nx * ny;
+  ly.t2 = P3;
+  ly.se = nx;
+  lz.nlines = nrhs * ny * nx;
+  lz.n0 = nx;
+  lz.n1 = ny;
+  lz.t0 = 1;
+  lz.t1 = nx;
+  lz.t2 = P3;
+  lz.se = nx * ny;
   // forward: E_x^{-1}, E_y^{-1}, E_z^{-1} + divide
   if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
+         if (fx) return fft_axis(static_cast<const double*>(in), static_cast<double*>(b1), X.fft[0], lx, EPI_STORE, ep, st);
          return mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, ep, st);
        })) != hipSuccess)
     return e;
   if ((e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
+         if (fy) return fft_axis(static_cast<const double*>(b1), static_cast<double*>(b2), Y.fft[0], ly, EPI_STORE, ep, st);
          return mode_left(pr, Y.sw[ip][0], ny, b1, pr, b2, pr, nrhs * nz, nx, EPI_STORE, ep, st);
        })) != hipSuccess)
     return e;
   if ((e = timed(p, HELM_STAGE_Z_FWD_DIV, st, [&] {
+         if (fz) return fft_axis(static_cast<const double*>(b2), static_cast<double*>(b1), Z.fft[0], lz, EPI_DIVIDE, ep, st);
          return mode_left(pr, Z.sw[ip][0], nz, b2, pr, b1, pr, nrhs, nx * ny, EPI_DIVIDE, ep, st);
        })) != hipSuccess)
     return e;
   // inverse: E_z, E_y, E_x
   if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
+         if (fz) return fft_axis(static_cast<const double*>(b1), static_cast<double*>(b2), Z.fft[1], lz, EPI_STORE, ep, st);
          return mode_left(pr, Z.sw[ip][1], nz, b1, pr, b2, pr, nrhs, nx * ny, EPI_STORE, ep, st);
        })) != hipSuccess)
     return e;
   if ((e = timed(p, HELM_STAGE_Y_INV, st, [&] {
+         if (fy) return fft_axis(static_cast<const double*>(b2), static_cast<double*>(b1), Y.fft[1], ly, EPI_STORE, ep, st);
          return mode_left(pr, Y.sw[ip][1], ny, b2, pr, b1, pr, nrhs * nz, nx, EPI_STORE, ep, st);
        })) != hipSuccess)
     return e;
   const Prec tout = epi_last == EPI_ACCUM ? P_F64 : pr;
   return timed(p, HELM_STAGE_X_INV, st, [&] {
+    if (fx && epi_last == EPI_STORE)
+      return fft_axis(static_cast<const double*>(b1), static_cast<double*>(out), X.fft[1], lx, EPI_STORE, ep, st);
     return mode_right(pr, X.sw[ip][1], nx, b1, pr, out, tout, nrhs * ny * nz, epi_last, ep, st);
   });
 }
@@ -797,7 +867,7 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
     const DevAxis& Y = *p->ax[1];
     const DevAxis& Z = *p->ax[2];
     const long long nx = p->m[0], ny = p->m[1], nz = p->m[2];
-    if (p->opts.method == HELM_TPF && !p->cyl) {
+    if (!p->thomas()) {  // TPF, and HELM_FFT (TPF with fast transforms on uniform axes)
       // f -> W -> u -> W -> u -> W -> u  (u may alias f: f is consumed by the first product)
       e = tpf_products(p, P_F64, f, W, u, u, EPI_STORE, nrhs, sig, nullptr, 0, st);
     } else {
@@ -956,6 +1026,15 @@ extern "C" helm_status helm_pressure_solve(helm_plan* p, const double* f, double
                                            helm_info* info) {
   if (!p || !p->all_neumann || p->sigma != 0.0) return HELM_EINVAL;
   return helm_solve(p, f, pr, nrhs, nullptr, ws, stream, info);
+}
+
+extern "C" helm_status helm_fast_axes(const helm_plan* p, int* mask) {
+  if (!p || !mask) return HELM_EINVAL;
+  *mask = 0;
+  if (p->opts.method == HELM_FFT && !p->cyl)
+    for (int d = 0; d < 3; ++d)
+      if (p->ax[d]->fft_ok) *mask |= 1 << d;
+  return HELM_OK;
 }
 
 extern "C" helm_status helm_profile_enable(helm_plan* p, int enable) {
