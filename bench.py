@@ -53,12 +53,32 @@ def build_workload(name):
     if name == "small_32":
         prob, f = workloads.workload_small_dirichlet()
         return prob, f, None, dict(tau=0.1)
+    if name == "uniform_256":
+        # the 256^3 mixed-precision workload on a uniform grid (beta = 0): the fast-transform
+        # path (method fft) beside the eigenvector products
+        prob = workloads.box_problem(256, 0.0, sigma=0.1, name="helmholtz_256cube_uniform_tau10")
+        f = workloads.rhs_normal(3, 1, prob.shape_xyz) / 10.0
+        return prob, f, None, dict(tau=10.0, stretch=0.0)
     raise SystemExit(f"unknown workload {name}")
 
 
-def stage_roofline(stage, ms, launches, N, npts, prec):
-    """Algorithmic flop and byte rates of one stage (per launch averages)."""
+def fft_flops(n):
+    """Algorithmic flops per point of one fast sine/cosine transform of n points: a complex DFT
+    of length 2n (5 L log2 L real flops per L points, the usual radix-2 count) plus the complex
+    pre- and post-twiddles, per input point."""
+    L = 2 * n
+    return (5.0 * L * np.log2(L) + 12.0 * n) / n
+
+
+def stage_roofline(stage, ms, launches, N, npts, prec, fast=()):
+    """Algorithmic flop and byte rates of one stage (per launch averages).  fast: the stages run by
+    the fast transform (HELM_FFT), which read and write FP64 once per point and are HBM-bound."""
     avg_s = ms / launches / 1e3
+    if stage in fast:
+        flops = fft_flops(N[stage]) * npts
+        byts = 16 * npts
+        return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", avg_us=avg_s * 1e6,
+                    algorithmic_flops=flops, algorithmic_bytes=byts, algorithmic_tflops=flops / avg_s / 1e12)
     if stage in MODE_STAGES:
         flops = 2.0 * N[stage] * npts
         es = ELEM_BYTES[prec]
@@ -172,8 +192,9 @@ def sweep_errors(torch, prob, f_dev, golden, nrhs):
 
 def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     from paper_1107_2461_amd import Plan
-    prec = {"fp64": "fp64", "fp32_ir": "fp32_ir", "bf16_ir": "bf16_ir", "bf16x3_ir": "bf16x3_ir", "tpt": "fp64"}[path]
-    method = "tpt" if path == "tpt" else "tpf"
+    prec = {"fp64": "fp64", "fp32_ir": "fp32_ir", "bf16_ir": "bf16_ir", "bf16x3_ir": "bf16x3_ir", "tpt": "fp64",
+            "fft": "fp64"}[path]
+    method = {"tpt": "tpt", "fft": "fft"}.get(path, "tpf")
     plan = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma, loc=prob.loc, precision=prec, method=method)
     u = torch.empty_like(f_dev)
     ws = plan.workspace(nrhs, f_dev.device)
@@ -183,7 +204,13 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     N = dict(x_fwd=prob.shape_xyz[0], x_inv=prob.shape_xyz[0], y_fwd=prob.shape_xyz[1], y_inv=prob.shape_xyz[1],
              z_fwd_div=prob.shape_xyz[2], z_inv=prob.shape_xyz[2], x_fwd_rhs=prob.shape_xyz[0],
              z_inv_u=prob.shape_xyz[2])
-    lowp = {"fp64": "fp64", "tpt": "fp64", "fp32_ir": "fp32", "bf16_ir": "bf16", "bf16x3_ir": "bf16x3"}[path]
+    lowp = {"fp64": "fp64", "tpt": "fp64", "fft": "fp64", "fp32_ir": "fp32", "bf16_ir": "bf16",
+            "bf16x3_ir": "bf16x3"}[path]
+    fast = ()
+    if path == "fft":   # the stages of the axes on the fast transform
+        ax = plan.fast_axes()
+        fast = tuple(s for d, pair in enumerate((("x_fwd", "x_inv"), ("y_fwd", "y_inv"), ("z_fwd_div", "z_inv")))
+                     if d in ax for s in pair)
     npts = prob.npts * nrhs
     # 1) per-stage table from a short run with every launch bracketed by events
     prof_steps = max(1, min(steps, 5))
@@ -195,7 +222,7 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     stages = plan.profile_read()
     st = {}
     for name, (ms, n) in stages.items():
-        rl = stage_roofline(name, ms, n, N, npts, lowp)
+        rl = stage_roofline(name, ms, n, N, npts, lowp, fast)
         entry = dict(total_ms_per_step=ms / prof_steps, launches_per_step=n / prof_steps)
         if rl:
             entry.update(rl)
@@ -220,7 +247,7 @@ def run_path(torch, prob, f_dev, path, steps, warmup, golden, nrhs):
     timed = plan.profile_read()
     plan.profile(False)
     dms, dn = timed[dom]
-    dom_rl = stage_roofline(dom, dms, dn, N, npts, lowp)
+    dom_rl = stage_roofline(dom, dms, dn, N, npts, lowp, fast)
     dom_rl["frac"] = dom_rl["achieved"] / dom_rl["peak"]
     total_ms = ev0.elapsed_time(ev1)
     # 3) per-solve latency: the same solves, each between two events (torch's events fence the
@@ -581,6 +608,61 @@ def run_timestep(torch, args):
                                                note="Table 3, 100^3, Gr = 1e7, one vector CPU core"),
                 paths=paths)
     print(json.dumps(line))
+
+
+def run_cyl(torch, args):
+    """Cylindrical-coordinate solve (Section 6, eqs. 41-44): a full cylinder r <= 1 through the
+    axis, 256 radial cells (tanh-stretched), 256 periodic theta cells, 256 axial cells on [0, 2]
+    (stretched), Dirichlet at r = 1 and at both ends, tau = 10 (sigma = 0.1), f ~ N(0,1) / 10
+    (seed 3).  FP64: theta and z eigen-transforms (MFMA) and one radial Thomas solve per mode
+    pair.  Accuracy is the library operator's residual; parity against the oracle is in the GPU
+    tests (tests/test_gpu_cyl.py)."""
+    from paper_1107_2461_amd import DIRICHLET, NEUMANN, CylPlan
+    nr, nt, nz = 256, 256, 256
+    rf = workloads.stretched_faces(nr, 1.5, 0.0, 1.0)
+    tf = np.linspace(0.0, 2 * np.pi, nt + 1)
+    zf = workloads.stretched_faces(nz, 1.5, 0.0, 2.0)
+    plan = CylPlan((rf, tf, zf), (NEUMANN, NEUMANN, DIRICHLET), (DIRICHLET, NEUMANN, DIRICHLET), 0.1,
+                   theta_periodic=True)
+    f = torch.from_numpy(workloads.rhs_normal(3, 1, (nt, nz, nr)) / 10.0).to("cuda")   # [1, nr, nz, nt]
+    u = torch.empty_like(f)
+    ws = plan.workspace(1, f.device)
+    for _ in range(args.warmup):
+        plan.solve(f, out=u, workspace=ws)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(min(args.steps, 5)):
+        plan.solve(f, out=u, workspace=ws)
+    torch.cuda.synchronize()
+    stages = plan.profile_read()
+    plan.profile(False)
+    npts = nr * nt * nz
+    N = dict(x_fwd=nt, x_inv=nt, y_fwd=nz, y_inv=nz)
+    reps = min(args.steps, 5)
+    table = {}
+    for name, (ms, n) in stages.items():
+        ent = dict(ms_per_step=ms / reps, launches_per_step=n / reps)
+        rl = stage_roofline(name, ms, n, N, npts, "fp64") if name in N or name == "thomas" else None
+        if rl:
+            ent.update(rl)
+            ent["frac"] = rl["achieved"] / rl["peak"]
+        table[name] = ent
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        plan.solve(f, out=u, workspace=ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    r = float((f - plan.apply(u)).norm() / f.norm())
+    log(f"[cyl] {nr}x{nt}x{nz}: {ms:.3f} ms per solve, {npts / ms / 1e-3:.3e} grid-pts/s, residual {r:.1e}")
+    print(json.dumps(dict(metric="grid-pts/s per cylindrical Helmholtz solve (FP64)", value=npts / (ms * 1e-3),
+                          unit="grid-pts/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
+                          higher_is_better=True, dtype="f64", data="synthetic",
+                          config=dict(workload="cylinder_256r_256theta_256z_tau10", r=[0.0, 1.0], z=[0.0, 2.0],
+                                      stretch=1.5, theta="periodic uniform", sigma=0.1),
+                          rel_residual_helm_apply=r, stages=table)))
 
 
 def run_shard(torch, args, gpus=8):
@@ -986,7 +1068,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="mixed_256",
-                    help="mixed_256 (default), multirhs_128, small_32, pressure, serving, peaks, timestep, shard8")
+                    help="mixed_256 (default), multirhs_128, small_32, uniform_256 (use --paths fft,fp64,...), "
+                         "cyl_256, pressure, serving, peaks, timestep, shard8")
     ap.add_argument("--paths", default="fp64,bf16x3_ir,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1028,6 +1111,9 @@ def main():
         return
     if args.workload == "shard8":
         run_shard(torch, args)
+        return
+    if args.workload == "cyl_256":
+        run_cyl(torch, args)
         return
     prob, f, gname, extra = build_workload(args.workload)
     golden = None
@@ -1079,10 +1165,10 @@ def main():
         cpu_tpf = cpu_tpf_baseline(prob, f, golden)
     line = dict(metric="grid-pts/s per Helmholtz solve @1e-10 rel err", value=b["pts_per_s"], unit="grid-pts/s",
                 n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=b["ms_per_step"],
-                higher_is_better=True, scaling="weak", vs_baseline=None, dtype=b["precision"] if best != "fp64"
-                else "f64", data="synthetic",
-                config=dict(workload=prob.name, grid=list(prob.shape_xyz), stretch=1.5, nrhs=nrhs,
-                            sigma=prob.sigma, path=best, **extra),
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64" if b["precision"] == "fp64" else b["precision"], data="synthetic",
+                config={**dict(workload=prob.name, grid=list(prob.shape_xyz), stretch=1.5, nrhs=nrhs,
+                               sigma=prob.sigma, path=best), **extra},
                 p50_ms=b["p50_ms"], p99_ms=b["p99_ms"], roofline=roofline, cpu_baseline=cpu, cpu_tpf_baseline=cpu_tpf, sweep_errors=swe,
                 paths={k: {kk: vv for kk, vv in v.items()} for k, v in results.items()})
     print(json.dumps(line))

@@ -64,7 +64,7 @@ __device__ inline void stage(d2* buf, int L, int B, int Ns, const d2* __restrict
     const int k = j % Ns;
     d2 v[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = buf[b * L + j + q * nb];
+    for (int q = 0; q < R; ++q) v[q] = buf[fft_lds_index(b * L + j + q * nb)];
     if (k != 0) {
 #pragma unroll
       for (int q = 1; q < R; ++q) v[q] = cmul(v[q], W[q * k * step]);
@@ -110,7 +110,7 @@ __device__ inline void stage(d2* buf, int L, int B, int Ns, const d2* __restrict
   for (int u = 0; u < U; ++u)
     if (dst[u] >= 0) {
 #pragma unroll
-      for (int p = 0; p < R; ++p) buf[dst[u] + p * Ns] = res[u][p];
+      for (int p = 0; p < R; ++p) buf[fft_lds_index(dst[u] + p * Ns)] = res[u][p];
     }
   __syncthreads();
 }
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
       const d2 pq = pre[q];
       y = d2{x * pq.x, x * pq.y};
     }
-    buf[b * L + q] = y;
+    buf[fft_lds_index(b * L + q)] = y;
   }
   __syncthreads();
   int Ns = 1;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
       b = idx - p * B;
     }
     if (b >= nl) continue;
-    const d2 Y = buf[b * L + p];
+    const d2 Y = buf[fft_lds_index(b * L + p)];
     const d2 ps = post[p];
     double v = ps.x * Y.x - ps.y * Y.y;
     if constexpr (EPI == EPI_DIVIDE) {
@@ -200,6 +200,169 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
       v = divide_den(v, ep, ep.lamz[p] + (ep.lamx[a] + ep.lamy[bb] + ep.sigma[rr]));
     }
     out[lbase[b] + p * ln.se] = v;
+  }
+}
+
+// ---- power-of-two lengths: L, the lines per workgroup and every stage's radix and stride are
+// compile-time constants, so the index arithmetic has no runtime divisions.
+template <int L>
+constexpr int pow2_lines() {
+  return kFftBuf / L < kFftMaxLines ? kFftBuf / L : kFftMaxLines;
+}
+
+template <int R, int L, int Ns>
+__device__ inline void stage_c(d2* buf, const d2* __restrict__ W) {
+  constexpr int B = pow2_lines<L>();
+  constexpr int nb = L / R;
+  constexpr int total = B * nb;
+  constexpr int U = (total + 255) / 256;
+  constexpr int step = L / (Ns * R);
+  d2 res[U][R];
+  int dst[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = threadIdx.x + 256 * u;
+    dst[u] = -1;
+    if (total % 256 != 0 && t >= total) continue;
+    const int b = t / nb, j = t % nb;
+    const int k = j % Ns;
+    d2 v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = buf[fft_lds_index(b * L + j + q * nb)];
+    if (Ns > 1 && k != 0) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[q] = cmul(v[q], W[q * k * step]);
+    }
+    if constexpr (R == 2) {
+      res[u][0] = v[0] + v[1];
+      res[u][1] = v[0] - v[1];
+    } else if constexpr (R == 4) {
+      dft4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) res[u][p] = v[p];
+    } else {
+      d2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+      dft4(e0, e1, e2, e3);
+      dft4(o0, o1, o2, o3);
+      const double c = 0.70710678118654752440;
+      const d2 t1 = d2{c * (o1.x - o1.y), c * (o1.x + o1.y)};
+      const d2 t2 = mul_i(o2);
+      const d2 t3 = d2{-c * (o3.x + o3.y), c * (o3.x - o3.y)};
+      res[u][0] = e0 + o0;
+      res[u][4] = e0 - o0;
+      res[u][1] = e1 + t1;
+      res[u][5] = e1 - t1;
+      res[u][2] = e2 + t2;
+      res[u][6] = e2 - t2;
+      res[u][3] = e3 + t3;
+      res[u][7] = e3 - t3;
+    }
+    dst[u] = b * L + (j / Ns) * Ns * R + k;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (dst[u] >= 0) {
+#pragma unroll
+      for (int p = 0; p < R; ++p) buf[fft_lds_index(dst[u] + p * Ns)] = res[u][p];
+    }
+  __syncthreads();
+}
+
+// radix 8 while at least 8 remain, then one radix-4 or radix-2 stage
+template <int L, int Ns>
+__device__ inline void stages_pow2(d2* buf, const d2* __restrict__ W) {
+  constexpr int rem = L / Ns;
+  if constexpr (rem >= 8) {
+    stage_c<8, L, Ns>(buf, W);
+    stages_pow2<L, Ns * 8>(buf, W);
+  } else if constexpr (rem == 4) {
+    stage_c<4, L, Ns>(buf, W);
+  } else if constexpr (rem == 2) {
+    stage_c<2, L, Ns>(buf, W);
+  }
+}
+
+template <int EPI, int L>
+__global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in, double* __restrict__ out,
+                                                  FftTables t, FftLines ln, EpiArgs ep) {
+  constexpr int B = pow2_lines<L>();
+  __shared__ d2 buf[fft_lds_index(B * L - 1) + 1];
+  __shared__ long long lbase[B];
+  const int N = t.N;
+  const long long line0 = static_cast<long long>(blockIdx.x) * B;
+  const int nl = static_cast<int>(min<long long>(B, ln.nlines - line0));
+  if (threadIdx.x < nl) {
+    const long long line = line0 + threadIdx.x;
+    const long long a0 = line % ln.n0, rest = line / ln.n0;
+    const long long a1 = rest % ln.n1, a2 = rest / ln.n1;
+    lbase[threadIdx.x] = a2 * ln.t2 + a1 * ln.t1 + a0 * ln.t0;
+  }
+  __syncthreads();
+  const d2* pre = reinterpret_cast<const d2*>(t.pre);
+  const d2* post = reinterpret_cast<const d2*>(t.post);
+  const d2* W = reinterpret_cast<const d2*>(t.W);
+  const bool contig = ln.se == 1;
+  constexpr int UL = (B * L + 255) / 256;
+#pragma unroll 4
+  for (int u = 0; u < UL; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    if ((B * L) % 256 != 0 && idx >= B * L) break;
+    const int b = contig ? idx / L : idx % B;
+    const int q = contig ? idx % L : idx / B;
+    d2 y = d2{0.0, 0.0};
+    if (q < N && b < nl) {
+      const double x = in[lbase[b] + q * ln.se];
+      const d2 pq = pre[q];
+      y = d2{x * pq.x, x * pq.y};
+    }
+    buf[fft_lds_index(b * L + q)] = y;
+  }
+  __syncthreads();
+  stages_pow2<L, 1>(buf, W);
+  constexpr int US = (B * L / 2 + 255) / 256;  // N <= L / 2 outputs per line
+#pragma unroll 4
+  for (int u = 0; u < US; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    if (idx >= B * N) break;
+    const int b = contig ? idx / N : idx % B;
+    const int p = contig ? idx % N : idx / B;
+    if (b >= nl) continue;
+    const d2 Y = buf[fft_lds_index(b * L + p)];
+    const d2 ps = post[p];
+    double v = ps.x * Y.x - ps.y * Y.y;
+    if constexpr (EPI == EPI_DIVIDE) {
+      const long long line = line0 + b;
+      const int a = static_cast<int>(line % ln.n0);
+      const long long rest = line / ln.n0;
+      const int bb = static_cast<int>(rest % ln.n1);
+      const int rr = static_cast<int>(rest / ln.n1);
+      v = divide_den(v, ep, ep.lamz[p] + (ep.lamx[a] + ep.lamy[bb] + ep.sigma[rr]));
+    }
+    out[lbase[b] + p * ln.se] = v;
+  }
+}
+
+template <int EPI>
+bool launch_pow2(int L, dim3 grid, const double* in, double* out, const FftTables& t, const FftLines& ln,
+                 const EpiArgs& ep, hipStream_t st) {
+  switch (L) {
+#define HELM_FFT_CASE(LL)                                                                           \
+  case LL:                                                                                          \
+    if (t.lines != pow2_lines<LL>()) return false;                                                  \
+    hipLaunchKernelGGL((k_fft_pow2<EPI, LL>), grid, dim3(256), 0, st, in, out, t, ln, ep);          \
+    return true;
+    HELM_FFT_CASE(8)
+    HELM_FFT_CASE(16)
+    HELM_FFT_CASE(32)
+    HELM_FFT_CASE(64)
+    HELM_FFT_CASE(128)
+    HELM_FFT_CASE(256)
+    HELM_FFT_CASE(512)
+    HELM_FFT_CASE(1024)
+#undef HELM_FFT_CASE
+    default:
+      return false;
   }
 }
 
@@ -317,9 +480,13 @@ hipError_t fft_axis(const double* in, double* out, const FftTables& t, const Fft
     if (r != 2 && r != 4 && r != 8 && r != 3 && r != 5 && r != 7) return hipErrorInvalidValue;
     odd = odd || (r & 1);
   }
-  const size_t lds = static_cast<size_t>(t.lines) * t.L * 2 * sizeof(double);
+  const size_t lds = static_cast<size_t>(fft_lds_index(t.lines * t.L - 1) + 1) * 2 * sizeof(double);
   const dim3 grid(static_cast<unsigned>(blocks)), block(256);
   if (epi != EPI_DIVIDE && epi != EPI_STORE) return hipErrorInvalidValue;
+  // power-of-two lengths: the compile-time kernel
+  if (!odd && (epi == EPI_DIVIDE ? launch_pow2<EPI_DIVIDE>(t.L, grid, in, out, t, ln, ep, st)
+                                 : launch_pow2<EPI_STORE>(t.L, grid, in, out, t, ln, ep, st)))
+    return hipGetLastError();
   if (epi == EPI_DIVIDE) {
     if (odd)
       hipLaunchKernelGGL((k_fft<EPI_DIVIDE, true>), grid, block, lds, st, in, out, t, ln, ep);
