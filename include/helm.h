@@ -415,6 +415,54 @@ void helm_server_destroy(helm_server* s);
 helm_status helm_sched_simulate(int n, const double* arrival, const double* service, const size_t* foot,
                                 int slots, size_t budget, double max_bypass_ms, double* admit, double* done);
 
+/* ---------------------------------------------------------------------------------------
+ * Time stepping (Section 5, eqs. 34-40): Boussinesq convection in a box on the MAC grid
+ * (pressure and temperature at the cell centres, velocity component d on the interior d-faces,
+ * no-slip walls), temperature T_lo at x = 0 and T_hi at x = 1, adiabatic elsewhere, Prandtl
+ * number Pr, Grashof number Gr.  One step of the second-order backward, incremental pressure-
+ * correction scheme of eqs. 37-40:
+ *   (3/(2dt) - kappa Lap) T1 = (4 T0 - Tm)/(2dt) - A_T(v0, T0)            kappa = 1/(Pr Gr^1/2)
+ *   (3/(2dt) - nu Lap) v*_d  = (4 v0_d - vm_d)/(2dt) - A_d(v0) - Grad_d p0 + [d = z] T1   nu = Gr^-1/2
+ *   -Lap dp = Div v* / dt;   v1 = v* + dt Grad dp;   p1 = p0 - dp
+ * with the FV Laplacian of helm_setup (the wall values of T entering through the boundary flux)
+ * and conservative central advection: A_T = sum_d (flux_hi - flux_lo) / w_d with face flux
+ * v_d times the mean of the two cells; A_d on the d-face control volume, with the flux ubar^2
+ * at the cell centres along d (ubar: the mean of the cell's two d-faces) and, across each other
+ * direction e, the e-velocity averaged over the two cells beside the d-face times v_d averaged
+ * over the two cells beside the e-face.  p1 subtracts dp: the update consistent with eq. 38's
+ * -Grad p and the correction of eq. 40 (eq. 40 as printed adds it).
+ * Fields are device FP64 arrays, x fastest: cells [nz][ny][nx]; v_d on its face grid (one fewer
+ * node along d).  Outputs may alias the step n-1 inputs (T1 = Tm, v1 = vm) and p1 may alias p0.
+ * --------------------------------------------------------------------------------------- */
+typedef struct helm_ts helm_ts;
+typedef struct {
+  const double* T0;         /* temperature at step n */
+  const double* Tm;         /* ... at step n - 1 */
+  const double* v0[3];      /* velocity components at step n */
+  const double* vm[3];      /* ... at step n - 1 */
+  const double* p0;         /* pressure at step n */
+  double* T1;               /* outputs: step n + 1 */
+  double* v1[3];
+  double* p1;
+} helm_ts_fields;
+
+/* Builds the temperature, three velocity and pressure plans (opts: their arithmetic and
+ * allocator; NULL = FP64 TPF) for the pressure cells of `grid` (loc ignored, n >= 3 per axis).
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+helm_status helm_ts_create(const helm_grid* grid, double Pr, double Gr, double dt, double T_lo, double T_hi,
+                           const helm_opts* opts, helm_ts** out);
+/* Workspace bytes of helm_ts_step (right-hand sides, divergence, pressure increment, one solve's
+ * workspace), 256-byte aligned, owned by the caller. */
+helm_status helm_ts_workspace_size(const helm_ts* ts, size_t* bytes);
+/* One time step on `stream`.  srv NULL: the five solves run on the stepper's plans, and the call
+ * is asynchronous unless the plans refine adaptively.  srv given: they are submitted to that
+ * server as requests (the temperature, then the three velocities together, then the pressure),
+ * each waited for on the host; the server must serve this stepper only (its completion records
+ * are consumed here).  info->sweeps: the low-precision solves performed (5 in FP64). */
+helm_status helm_ts_step(helm_ts* ts, const helm_ts_fields* fields, helm_server* srv, void* ws, void* stream,
+                         helm_info* info);
+void helm_ts_destroy(helm_ts* ts);
+
 /* Host-only helpers (no device needed), for checking the setup stage on any machine. */
 /* 1D operator of one axis: lower/diag/upper rows of A = V^{-1} K (each of length m, the
  * number of unknowns) and the control-volume widths vol[m].  Returns m in *m_out. */

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (BF16, BF16_IR, CELL, DIRICHLET, FACE, FP32, FP32_IR, FP64, NEUMANN, NULL_PAPER_EQ28,
                    NULL_PROJECT, TPF, TPT_Z, HelmError, check, load)
 
-__all__ = ["Plan", "CylPlan", "host_operator_cyl", "host_eigen_cyl", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
+__all__ = ["Plan", "CylPlan", "TimeStepper", "host_operator_cyl", "host_eigen_cyl", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
            "NEUMANN", "CELL", "FACE", "FP64", "FP32", "BF16", "FP32_IR", "BF16_IR", "TPF", "TPT_Z",
            "NULL_PROJECT", "NULL_PAPER_EQ28"]
 
@@ -548,6 +548,70 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class TimeStepper:
+    """One step of the paper's time integration (helm_ts_*; Section 5, eqs. 37-40) on the MAC
+    grid of the pressure cells `faces`: right-hand sides from the previous fields (time
+    derivative, advection, pressure gradient, buoyancy, heated walls T_lo at x = 0 and T_hi at
+    x = 1), one temperature, three velocity and one pressure solve, correction and update.
+    Fields are contiguous float64 CUDA tensors: cells (nz, ny, nx), velocities on
+    velocity_shapes()."""
+
+    def __init__(self, faces, Pr, Gr, dt, T_lo=0.5, T_hi=-0.5, precision="fp64", method="tpf", allocator=None):
+        lib = load()
+        g, self._faces = _grid(faces, (CELL,) * 3)
+        opts = _opts(precision, method, None, None, NULL_PROJECT, allocator)
+        h = C.c_void_p()
+        check(lib.helm_ts_create(C.byref(g), float(Pr), float(Gr), float(dt), float(T_lo), float(T_hi),
+                                 C.byref(opts), C.byref(h)), "helm_ts_create")
+        self._h = h
+        self.shape_xyz = tuple(len(f) - 1 for f in faces)
+        self._ws = None
+        self.last_info = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                load().helm_ts_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def cell_shape(self):
+        nx, ny, nz = self.shape_xyz
+        return (nz, ny, nx)
+
+    def velocity_shapes(self):
+        nx, ny, nz = self.shape_xyz
+        return (nz, ny, nx - 1), (nz, ny - 1, nx), (nz - 1, ny, nx)
+
+    def step(self, T0, Tm, v0, vm, p0, T1=None, v1=None, p1=None, server=None, stream=None):
+        """(T1, v1, p1) of eqs. 37-40 from the fields at steps n (T0, v0, p0) and n - 1 (Tm, vm).
+        server: a Server dedicated to this stepper, through which the five solves are run."""
+        torch = _torch()
+        for t, shp in [(T0, self.cell_shape()), (Tm, self.cell_shape()), (p0, self.cell_shape())] + \
+                list(zip(v0, self.velocity_shapes())) + list(zip(vm, self.velocity_shapes())):
+            if tuple(t.shape) != shp or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"field must be a contiguous float64 CUDA tensor of shape {shp}")
+        T1 = torch.empty_like(T0) if T1 is None else T1
+        v1 = [torch.empty_like(v) for v in v0] if v1 is None else list(v1)
+        p1 = torch.empty_like(p0) if p1 is None else p1
+        if self._ws is None:
+            n = C.c_size_t()
+            check(load().helm_ts_workspace_size(self._h, C.byref(n)), "helm_ts_workspace_size")
+            self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=T0.device)
+        fl = _lib.HelmTsFields()
+        fl.T0, fl.Tm, fl.p0 = T0.data_ptr(), Tm.data_ptr(), p0.data_ptr()
+        fl.T1, fl.p1 = T1.data_ptr(), p1.data_ptr()
+        for d in range(3):
+            fl.v0[d], fl.vm[d], fl.v1[d] = v0[d].data_ptr(), vm[d].data_ptr(), v1[d].data_ptr()
+        info = _lib.HelmInfo()
+        check(load().helm_ts_step(self._h, C.byref(fl), server._h if server is not None else None,
+                                  Plan._aligned(self._ws), _stream_ptr(stream), C.byref(info)), "helm_ts_step")
+        self.last_info = dict(solves=info.sweeps)
+        return T1, v1, p1
 
 
 def sched_simulate(arrival, service, footprint, slots, budget, max_bypass_ms=0.0):

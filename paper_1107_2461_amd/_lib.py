@@ -30,6 +30,11 @@ class HelmCylGrid(C.Structure):
     _fields_ = [("n", C.c_int * 3), ("faces", C.POINTER(C.c_double) * 3), ("theta_periodic", C.c_int)]
 
 
+class HelmTsFields(C.Structure):
+    _fields_ = [("T0", C.c_void_p), ("Tm", C.c_void_p), ("v0", C.c_void_p * 3), ("vm", C.c_void_p * 3),
+                ("p0", C.c_void_p), ("T1", C.c_void_p), ("v1", C.c_void_p * 3), ("p1", C.c_void_p)]
+
+
 class HelmBC(C.Structure):
     _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3)]
 
@@ -107,6 +112,11 @@ SIGNATURES = {
                                  C.POINTER(P)]),
     "helm_host_operator_cyl": (C.c_int, [C.c_int, C.c_int, DP, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
     "helm_host_eigen_cyl": (C.c_int, [C.c_int, C.c_int, DP, C.c_int, C.c_int, IP, DP, DP, DP]),
+    "helm_ts_create": (C.c_int, [C.POINTER(HelmGrid), C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.POINTER(HelmOpts), C.POINTER(P)]),
+    "helm_ts_workspace_size": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+    "helm_ts_step": (C.c_int, [P, C.POINTER(HelmTsFields), P, P, P, C.POINTER(HelmInfo)]),
+    "helm_ts_destroy": (None, [P]),
     "helm_host_operator_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP, DP]),
     "helm_host_eigen_1d": (C.c_int, [C.c_int, DP, C.c_int, C.c_int, C.c_int, IP, DP, DP, DP]),
 }

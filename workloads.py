@@ -183,3 +183,19 @@ def serving_problem(req) -> Problem:
     faces = tuple(stretched_faces(req["n"][d], req["beta"][d]) for d in range(3))
     return Problem(faces=faces, bc_lo=tuple(req["bc_lo"]), bc_hi=tuple(req["bc_hi"]),
                    sigma=req["sigma"], name=f"serve_{req['rid']}")
+
+
+def timestep_state(seed: int, n_xyz, amp: float = 0.1):
+    """Seeded fields of two time levels for one step of eqs. 37-40 on the MAC grid of n_xyz
+    pressure cells: (T0, Tm, v0, vm, p0) with T ~ U[-0.5, 0.5] at the cells, each velocity
+    component amp * N(0,1) on its interior faces, p ~ N(0,1) at the cells; arrays [nz, ny, nx]."""
+    nx, ny, nz = n_xyz
+    n = (nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    cell = (nz, ny, nx)
+    vel = [tuple(n[2 - a] - (1 if 2 - a == d else 0) for a in range(3)) for d in range(3)]
+    T0, Tm = rng.uniform(-0.5, 0.5, cell), rng.uniform(-0.5, 0.5, cell)
+    v0 = [amp * rng.standard_normal(s) for s in vel]
+    vm = [amp * rng.standard_normal(s) for s in vel]
+    p0 = rng.standard_normal(cell)
+    return T0, Tm, v0, vm, p0
