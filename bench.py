@@ -675,25 +675,35 @@ def run_shard(torch, args, gpus=8):
             for name, (ms, cnt) in st.items():
                 if name in keep:
                     per[name] = dict(ms_per_solve=ms / reps, launches_per_solve=cnt / reps, shape=tag)
+            if tag == "z-slab":
+                sweeps = pl.last_info["sweeps"]          # solves per refined solve, as timed
             del pl
         compute_ms = sum(v["ms_per_solve"] for v in per.values())
-        solves = 2 if prec.endswith("_ir") else 1
+        solves = sweeps if prec.endswith("_ir") else 1
         bytes_pt = 4 if prec.startswith("bf16x3") else 8
         sent = (n ** 3 / gpus) * (gpus - 1) / gpus * bytes_pt      # bytes each GPU sends per transpose
         a2a_us = sent / (7 * 153e9) * 1e6
         comm_ms = 2 * solves * a2a_us / 1e3
         key = prec if method == "tpf" else f"{prec}_{method}"
-        out[key] = dict(stages=per, compute_ms_per_gpu=compute_ms, alltoall_us_each_modeled=a2a_us,
-                        transposes_per_solve=2 * solves, projected_ms=compute_ms + comm_ms,
-                        projected_pts_per_s=n ** 3 / ((compute_ms + comm_ms) / 1e3))
+        out[key] = dict(stages=per, compute_ms_per_gpu=compute_ms, compute_pts_per_s=n ** 3 / gpus / (compute_ms / 1e3),
+                        alltoall_us_each_modeled=a2a_us, transposes_per_solve=2 * solves,
+                        projected_ms_modeled=compute_ms + comm_ms,
+                        projected_pts_per_s_modeled=n ** 3 / ((compute_ms + comm_ms) / 1e3))
         log(f"[bench] shard x{gpus} {key}: compute {compute_ms:.3f} ms per GPU, all-to-all {a2a_us:.1f} us each "
-            f"(modeled) x {2 * solves}, projected {compute_ms + comm_ms:.3f} ms per solve")
-    best = min(out, key=lambda k: out[k]["projected_ms"])
-    line = dict(metric=f"one GPU's share of a 256^3 solve over {gpus} GPUs: measured compute at the shard shapes "
-                       "plus modeled all-to-all", value=out[best]["projected_pts_per_s"], unit="grid-pts/s (projected)",
-                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=out[best]["projected_ms"],
-                higher_is_better=True, scaling="strong", vs_baseline=None, dtype=best, data="synthetic",
-                config=dict(workload=f"shard_256cube_x{gpus}", slab=[n, n, m], path=best), paths=out)
+            f"(modeled) x {2 * solves}, projected (modeled) {compute_ms + comm_ms:.3f} ms per solve")
+    best = min(out, key=lambda k: out[k]["compute_ms_per_gpu"])
+    line = dict(metric=f"one GPU's share of a 256^3 solve over {gpus} GPUs: grid-pts/s of the measured compute at "
+                       "the shard shapes (its 1/8 of the points)", value=out[best]["compute_pts_per_s"],
+                unit="grid-pts/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=out[best]["compute_ms_per_gpu"], higher_is_better=True, scaling="strong", vs_baseline=None,
+                dtype=best, data="synthetic",
+                config=dict(workload=f"shard_256cube_x{gpus}", slab=[n, n, m], path=best),
+                projected_modeled=dict(note="measured compute plus modeled all-to-all transposes (not built), no "
+                                            "overlap", ms_per_solve=out[best]["projected_ms_modeled"],
+                                       pts_per_s=out[best]["projected_pts_per_s_modeled"]),
+                accuracy_note="the slab solves are timed on random right-hand sides and not compared with the "
+                              "oracle (the full-size and slab-shaped solves are, in the GPU tests)",
+                paths=out)
     print(json.dumps(line))
 
 
