@@ -781,6 +781,51 @@ def same_grid_burst(torch, prec, args, n_req=192, n=64):
     return res
 
 
+def same_shape_burst(torch, prec, args, n_req=128, n=64):
+    """Many one-RHS requests on different grids of one shape (each its own per-axis stretch from
+    the serving set and its own shift), submitted back to back: the server solves queued
+    requests of one shape together as a grouped solve (one launch per stage, each right-hand
+    side with its own plan's eigenbases).  Compared with the same solves issued one at a time,
+    each on its own plan."""
+    from paper_1107_2461_amd import Plan, Server
+    b = workloads.SERVING_BETAS
+    combos = [(b[i % 5], b[(i // 5) % 5], b[(i // 25) % 5]) for i in range(n_req)]
+    probs = [workloads.Problem(faces=tuple(workloads.stretched_faces(n, c[d]) for d in range(3)), sigma=1.0)
+             for c in combos]
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    fs = torch.randn((n_req, 1, n, n, n), generator=gen, device="cuda", dtype=torch.float64)
+    sig = np.logspace(-1, 2, n_req)
+    res = {}
+    srv = Server(args.serve_budget_gb << 30, slots=args.serve_slots, precision=prec, max_bypass_ms=20.0)
+    for rnd in range(2):   # the first round builds the plans
+        us = torch.empty_like(fs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n_req):
+            srv.submit(i, probs[i].faces, fs[i], us[i], [float(sig[i])], probs[i].bc_lo, probs[i].bc_hi)
+        srv.drain()
+        span = time.perf_counter() - t0
+        recs = srv.poll(max_records=n_req + 8)
+    srv.close()
+    res.update(requests=n_req, grid=[n, n, n], distinct_grids=len(set(combos)), server_pts_per_s=n_req * n ** 3 / span,
+               server_ms=span * 1e3, solves=len({(r["slot"], r["t_done"]) for r in recs}),
+               mean_batch=float(np.mean([r["batch"] for r in recs])), failed=sum(r["status"] != 0 for r in recs))
+    plans = {c: Plan(pr.faces, pr.bc_lo, pr.bc_hi, 1.0, precision=prec) for c, pr in zip(combos, probs)}
+    ws = next(iter(plans.values())).workspace(1, fs.device)
+    u1 = torch.empty_like(fs[0])
+    for i in range(3):
+        plans[combos[i]].solve(fs[i], out=u1, sigma=[float(sig[i])], workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_req):
+        plans[combos[i]].solve(fs[i], out=u1, sigma=[float(sig[i])], workspace=ws)
+    torch.cuda.synchronize()
+    span1 = time.perf_counter() - t0
+    res.update(one_at_a_time_pts_per_s=n_req * n ** 3 / span1, one_at_a_time_ms=span1 * 1e3)
+    del plans
+    return res
+
+
 def run_serving(torch, args):
     """Serving stream: Poisson arrivals of mixed solve requests through the continuous-batching server."""
     from paper_1107_2461_amd import Server
@@ -841,6 +886,7 @@ def run_serving(torch, args):
                          plans_built=stats["plan_misses"],
                          plan_setup_ms_mean=1e3 * stats["setup_seconds"] / max(1, stats["plan_misses"]))
         out[prec]["same_grid_burst"] = same_grid_burst(torch, prec, args)
+        out[prec]["same_shape_burst"] = same_shape_burst(torch, prec, args)
         log(f"[serve] {prec}: {out[prec]}")
     best = max(out, key=lambda k: out[k]["pts_per_s"])
     line = dict(metric="grid-pts/s per Helmholtz solve @1e-10 rel err (serving stream); p50/p99 latency",
@@ -877,6 +923,21 @@ PROFILE_TRACE_128 = ("rocprofv3 --kernel-trace --stats --output-format csv -d {d
 # preconditioners and TPF / TPT velocity solves, and the Stokes solve (192 x 160 x 224 cells)
 PROFILE_TRACE_PRESSURE = ("rocprofv3 --kernel-trace --stats --output-format csv -d {d}/ktp -o kt -- "
                           "python -u bench.py --workload pressure --steps 1 --warmup 1")
+# kernel durations of the variants beside the hot path: (run directory, command, title, summary file)
+PROFILE_TRACE_VARIANTS = (
+    ("ktc", "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/ktc -o kt -- "
+            "python -u bench.py --workload cyl_256 --steps 5 --warmup 1",
+     "cylinder 256 (r) x 256 (theta, periodic) x 256 (z), tau = 10, FP64: theta and z transforms, "
+     "radial Thomas solves (Section 6, eqs. 41-44)", "kernel_stats_cylinder_256cube.md"),
+    ("ktu", "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/ktu -o kt -- "
+            "python -u bench.py --workload uniform_256 --paths fft,fp64 --steps 5 --warmup 1 --no-cpu-baseline",
+     "uniform 256^3 Dirichlet, tau = 10, FP64: fast sine transforms (method fft) beside the eigenvector "
+     "products", "kernel_stats_fft_uniform_256cube.md"),
+    ("ktt", "rocprofv3 --kernel-trace --stats --output-format csv -d {d}/ktt -o kt -- "
+            "python -u bench.py --workload timestep --steps 5 --warmup 2",
+     "one time step of eqs. 37-40 on 100^3 cells (Gr = 1e7, dt = 1e-3): right-hand sides, T, three "
+     "velocity and one pressure solve, correction", "kernel_stats_timestep_100cube.md"),
+)
 # HBM traffic of the Thomas pass (TPT, 128^3 x 3 RHS), one counter per run, with the same copy
 # calibration as the 256^3 runs.
 PROFILE_TRAFFIC_128 = tuple(
@@ -933,6 +994,8 @@ def summarize_profiles(d, copy_mb=1024, npts=256 ** 3, workload="256^3 Helmholtz
     kernel_table("ktp", "pressure workload, 192 x 160 x 224 cells: pressure solves, FGMRES on the pressure "
                  "matrix (eq. 9, tau = 100) and the Stokes solve (eq. 8)", PROFILE_TRACE_PRESSURE.format(d=d),
                  "kernel_stats_pressure_stokes_192x160x224.md")
+    for sub, cmd, title, out_name in PROFILE_TRACE_VARIANTS:
+        kernel_table(sub, title, cmd.format(d=d), out_name)
     # HBM traffic: per-dispatch counters, calibrated on the copy of copy_mb MiB
     per = {}
     scale = {}

@@ -175,6 +175,27 @@ helm_status helm_solve_noalloc(helm_plan* plan, const double* f, double* u, int 
  * transform (HELM_FFT plans with a uniform axis of a supported kind); 0 for other plans. */
 helm_status helm_fast_axes(const helm_plan* plan, int* mask);
 
+/* Grouped solve: the right-hand sides of several plans of one shape (different grids of the
+ * same cell counts: their own stretching, walls and shifts) solved together, one launch per
+ * stage of eqs. 25-29 over all of them; each right-hand side is multiplied by its own plan's
+ * eigenbases and divided by its own plan's eigenvalues.  The time stepper's solves and a
+ * stream of requests on a few grid sizes are the intended use (Section 5, eqs. 37-40).
+ *   plans[i], i < nplans: nrhs[i] right-hand sides each (sum <= 64).  Every plan must be
+ *     Cartesian, method HELM_TPF, precision FP64 or BF16X3(_IR), and share the first plan's
+ *     unknown counts, device, precision, ir_tol, max_sweeps and null_mode; else EINVAL.
+ *   f, u: device, the right-hand sides of plans[0], then plans[1], ... in the layout of
+ *     helm_solve ([sum nrhs][nz][ny][nx]); sigma: host, one shift per right-hand side
+ *     (nullable: each plan's setup shift).
+ *   ws: device workspace of helm_group_workspace_size bytes, 256-byte aligned; it also holds
+ *     the per-RHS operand table, which the call writes on `stream` before the products.
+ * Semantics, errors and refinement as helm_solve (the refinement loop stops when every
+ * right-hand side has converged).  A low-precision group with an all-Neumann plan at
+ * sigma = 0 (projection) returns EINVAL: solve that right-hand side on its own.  If every
+ * plans[i] is the same plan this is helm_solve with the summed right-hand-side count. */
+helm_status helm_group_workspace_size(helm_plan* const* plans, int nplans, const int* nrhs, size_t* bytes);
+helm_status helm_solve_group(helm_plan* const* plans, int nplans, const int* nrhs, const double* f, double* u,
+                             const double* sigma, void* ws, void* stream, helm_info* info);
+
 /* Hu = (sigma I - Lap_h) u with the FP64 7-point operator (the Kronecker sum of eq. 29),
  * device pointers [nrhs][nz][ny][nx]; asynchronous.  Hu must not alias u. */
 helm_status helm_apply(const helm_plan* plan, const double* u, double* Hu, int nrhs,

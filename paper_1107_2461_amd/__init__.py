@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (BF16, BF16_IR, CELL, DIRICHLET, FACE, FP32, FP32_IR, FP64, NEUMANN, NULL_PAPER_EQ28,
                    NULL_PROJECT, TPF, TPT_Z, HelmError, check, load)
 
-__all__ = ["Plan", "CylPlan", "TimeStepper", "host_operator_cyl", "host_eigen_cyl", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
+__all__ = ["Plan", "CylPlan", "TimeStepper", "solve_group", "group_workspace_bytes", "host_operator_cyl", "host_eigen_cyl", "PressureMatrix", "Server", "TorchAllocator", "torch_allocator", "sched_simulate", "load", "HelmError", "host_operator_1d", "host_eigen_1d", "DIRICHLET",
            "NEUMANN", "CELL", "FACE", "FP64", "FP32", "BF16", "FP32_IR", "BF16_IR", "TPF", "TPT_Z",
            "NULL_PROJECT", "NULL_PAPER_EQ28"]
 
@@ -612,6 +612,51 @@ class TimeStepper:
                                   Plan._aligned(self._ws), _stream_ptr(stream), C.byref(info)), "helm_ts_step")
         self.last_info = dict(solves=info.sweeps)
         return T1, v1, p1
+
+
+def _group_args(plans, nrhs):
+    hs = (C.c_void_p * len(plans))(*[p._h for p in plans])
+    ns = (C.c_int * len(plans))(*[int(n) for n in nrhs])
+    return C.cast(hs, C.POINTER(C.c_void_p)), C.cast(ns, _lib.IP)
+
+
+def group_workspace_bytes(plans, nrhs):
+    """helm_group_workspace_size for nrhs[i] right-hand sides of plans[i]."""
+    hs, ns = _group_args(plans, nrhs)
+    n = C.c_size_t()
+    check(load().helm_group_workspace_size(hs, len(plans), ns, C.byref(n)), "helm_group_workspace_size")
+    return n.value
+
+
+def solve_group(plans, f, nrhs=None, out=None, sigma=None, stream=None, workspace=None, info=None):
+    """helm_solve_group: the right-hand sides of several plans of one shape in one solve (one
+    launch per stage).  f: float64 CUDA tensor [sum nrhs, nz, ny, nx], the right-hand sides of
+    plans[0] first; nrhs: per plan (default 1 each); sigma: one shift per right-hand side
+    (default: each plan's own).  Returns u (and fills `info`, a dict, when given)."""
+    torch = _torch()
+    plans = list(plans)
+    nrhs = [1] * len(plans) if nrhs is None else [int(n) for n in nrhs]
+    if len(nrhs) != len(plans):
+        raise ValueError("nrhs must give one count per plan")
+    total = sum(nrhs)
+    if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous() or f.dim() != 4 or f.shape[0] != total:
+        raise ValueError("f must be a contiguous float64 CUDA tensor [sum nrhs, nz, ny, nx]")
+    u = torch.empty_like(f) if out is None else out
+    hs, ns = _group_args(plans, nrhs)
+    if workspace is None:
+        workspace = torch.empty(group_workspace_bytes(plans, nrhs) + 256, dtype=torch.uint8, device=f.device)
+    sig = None
+    if sigma is not None:
+        sarr = (C.c_double * total)(*[float(s) for s in np.broadcast_to(np.asarray(sigma, float), (total,))])
+        sig = C.cast(sarr, _lib.DP)
+    hi = _lib.HelmInfo()
+    st = load().helm_solve_group(hs, len(plans), ns, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), sig,
+                                 Plan._aligned(workspace), _stream_ptr(stream), C.byref(hi))
+    if info is not None:
+        info.update(sweeps=hi.sweeps, last_correction=hi.last_correction,
+                    converged=None if hi.converged < 0 else bool(hi.converged))
+    check(st, "helm_solve_group")
+    return u
 
 
 def sched_simulate(arrival, service, footprint, slots, budget, max_bypass_ms=0.0):

@@ -80,6 +80,8 @@ SIGNATURES = {
     "helm_solve_noalloc": (C.c_int, [P, P, P, C.c_int, DP, P, C.POINTER(HelmInfo)]),
     "helm_apply": (C.c_int, [P, P, P, C.c_int, DP, P]),
     "helm_fast_axes": (C.c_int, [P, IP]),
+    "helm_group_workspace_size": (C.c_int, [C.POINTER(P), C.c_int, IP, C.POINTER(C.c_size_t)]),
+    "helm_solve_group": (C.c_int, [C.POINTER(P), C.c_int, IP, P, P, DP, P, P, C.POINTER(HelmInfo)]),
     "helm_get_eigen": (C.c_int, [P, C.c_int, IP, DP, DP, DP]),
     "helm_destroy": (None, [P]),
     "helm_pressure_setup": (C.c_int, [C.POINTER(HelmGrid), C.POINTER(HelmOpts), C.POINTER(P)]),

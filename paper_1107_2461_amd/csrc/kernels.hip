@@ -98,6 +98,7 @@ hipError_t mode_left(Prec p, const void* Msw, int K, const void* X, Prec tin, vo
   if (epi != EPI_STORE && epi != EPI_DIVIDE) return hipErrorInvalidValue;
   if ((S * Nn + 15) / 16 > 0x7fffffffLL) return hipErrorInvalidValue;
   if (p == P_F64) return mode_left_f64(ci, Msw, K, X, Y, S, Nn, epi, ep, st);
+  if (ep.msw_rhs) return hipErrorInvalidValue;  // grouped solves: FP64 and split-BF16 only
   if (p == P_F32) return mode_left_f32(ci, Msw, K, X, Y, S, Nn, epi, ep, st);
   return mode_left_bf16(ci, Msw, K, X, Y, S, Nn, epi, ep, st);
 }
@@ -117,6 +118,7 @@ hipError_t mode_right(Prec p, const void* Msw, int K, const void* X, Prec tin, v
   const int vw = p == P_BF16 ? 8 : 4;  // elements per vector load of one row
   const bool vec = (K % vw == 0) && (reinterpret_cast<uintptr_t>(X) % (vw * elem_bytes(p)) == 0);
   if (p == P_F64) return mode_right_f64(ci, Msw, K, X, Y, Mrows, epi, vec, ep, st);
+  if (ep.msw_rhs) return hipErrorInvalidValue;  // grouped solves: FP64 and split-BF16 only
   if (p == P_F32) return mode_right_f32(ci, Msw, K, X, Y, Mrows, epi, vec, ep, st);
   return mode_right_bf16(ci, Msw, K, X, Y, Mrows, epi, vec, ep, st);
 }
@@ -391,7 +393,10 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
   const int ic = iok ? i : a.nx - 1;  // lanes past the end load a valid column, store nothing
   const long long plane = static_cast<long long>(a.nx) * a.ny;
   const long long rbase = static_cast<long long>(r) * plane * a.nz;
-  const double cxl = a.cx[3 * ic], cxd = a.cx[3 * ic + 1], cxu = a.cx[3 * ic + 2];
+  const double* __restrict__ cx = a.cx_rhs ? a.cx_rhs[r] : a.cx;
+  const double* __restrict__ cy = a.cy_rhs ? a.cy_rhs[r] : a.cy;
+  const double* __restrict__ cz = a.cz_rhs ? a.cz_rhs[r] : a.cz;
+  const double cxl = cx[3 * ic], cxd = cx[3 * ic + 1], cxu = cx[3 * ic + 2];
   const bool xper = CYL && a.xper;
   const bool hx_lo = xper || ic > 0, hx_hi = xper || ic + 1 < a.nx;
   int jr[JS + 2];  // rows j0-1 .. j0+JS, clamped into the grid
@@ -401,10 +406,10 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
 #pragma unroll
   for (int s = 0; s < JS; ++s) {
     const int j = jr[s + 1];
-    cyl[s] = (j0 + s > 0 && j0 + s < a.ny) ? a.cy[3 * j] : 0.0;
-    cyu[s] = (j0 + s + 1 < a.ny) ? a.cy[3 * j + 2] : 0.0;
+    cyl[s] = (j0 + s > 0 && j0 + s < a.ny) ? cy[3 * j] : 0.0;
+    cyu[s] = (j0 + s + 1 < a.ny) ? cy[3 * j + 2] : 0.0;
     // Cartesian: sigma + x and y diagonals; CYL: the x diagonal is added per plane, scaled
-    dxy[s] = CYL ? a.sigma[r] + a.cy[3 * j + 1] : a.sigma[r] + cxd + a.cy[3 * j + 1];
+    dxy[s] = CYL ? a.sigma[r] + cy[3 * j + 1] : a.sigma[r] + cxd + cy[3 * j + 1];
   }
   const TU* ucol = u + rbase + ic;
   auto at = [&](int k, int s) { return ucol + k * plane + static_cast<long long>(jr[s]) * a.nx; };
@@ -432,7 +437,7 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
     const bool has_up = k + 1 < a.nz;
 #pragma unroll
     for (int s = 0; s < JS + 2; ++s) up[s] = has_up ? *at(k + 1, s) : TU(0);
-    const double czl = a.cz[3 * k], czd = a.cz[3 * k + 1], czu = a.cz[3 * k + 2];
+    const double czl = cz[3 * k], czd = cz[3 * k + 1], czu = cz[3 * k + 2];
     const double xsk = CYL ? a.xscale[k] : 1.0;
 #pragma unroll
     for (int s = 0; s < JS; ++s) {
@@ -463,8 +468,10 @@ hipError_t stencil_any(int mode, const TU* u, const double* f, void* out, Prec t
                        hipStream_t st) {
   const long long n = static_cast<long long>(a.nx) * a.ny * a.nz * a.nrhs;
   if (n == 0) return hipSuccess;
-  // the cylindrical operator is built for FP64 u and output only
-  if (a.xscale && (mode == 2 || !std::is_same<TU, double>::value || tout != P_F64)) return hipErrorInvalidValue;
+  // the cylindrical operator is built for FP64 u and output only, and is never grouped
+  if (a.xscale && (mode == 2 || !std::is_same<TU, double>::value || tout != P_F64 || a.cx_rhs))
+    return hipErrorInvalidValue;
+  if (!a.cx_rhs != !a.cy_rhs || !a.cx_rhs != !a.cz_rhs) return hipErrorInvalidValue;
   if (mode == 2) {
     const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
     if (tout == P_F64)
@@ -983,6 +990,28 @@ hipError_t scale(double* y, const double* x, double a, long long n, hipStream_t 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, y, x, a, n);
   return hipGetLastError();
+}
+
+namespace {
+struct PtrBlock {
+  const void* p[kPtrBlock];
+};
+__global__ __launch_bounds__(256) void k_write_ptrs(PtrBlock b, int n, const void** dst) {
+  // vector stores of the argument block into global memory
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = b.p[i];
+}
+}  // namespace
+
+hipError_t write_ptrs(const void* const* src, int n, const void** dst, hipStream_t st) {
+  for (int o = 0; o < n; o += kPtrBlock) {
+    PtrBlock b{};
+    const int m = n - o < kPtrBlock ? n - o : kPtrBlock;
+    for (int i = 0; i < m; ++i) b.p[i] = src[o + i];
+    hipLaunchKernelGGL(k_write_ptrs, dim3(1), dim3(256), 0, st, b, m, dst + o);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace helm

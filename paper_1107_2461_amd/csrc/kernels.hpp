@@ -43,7 +43,22 @@ struct EpiArgs {
   long long rows_per_rhs = 1;     // rows of the x-mode matrix per RHS (accumulate)
   int accum_zero = 0;             // accumulate into zero instead of the current u
   double sigma[kMaxRhs];          // per-RHS shift
+  // Grouped solve (right-hand sides of several plans of one shape in one launch): per-RHS
+  // device tables of the operand and of the eigenvalue vectors, which replace Msw and the
+  // pointers above; `span` is the extent of one RHS in the launch's tiled dimension (rows of
+  // the right and rotating forms, columns of the left form), and every workgroup tile must lie
+  // inside one RHS (the launchers refuse a tiling that does not divide span).  NULL: one plan.
+  const void* const* msw_rhs = nullptr;
+  const double* const* lamx_rhs = nullptr;
+  const double* const* lamy_rhs = nullptr;
+  const double* const* lamz_rhs = nullptr;
+  const double* const* lamxy_rhs = nullptr;
+  long long span = 0;
 };
+// Whether a tiling of `tile` rows or columns serves the launch (always, unless grouped).
+inline bool group_tiles_ok(const EpiArgs& ep, long long tile) {
+  return !ep.msw_rhs || (ep.span > 0 && ep.span % tile == 0);
+}
 
 // Bytes of one swizzled operand matrix (rows x k padded to the kernel's blocking).
 size_t swizzled_bytes(Prec p, int K);
@@ -110,6 +125,10 @@ struct StencilArgs {
   // and last upper entries couple to the other end).  xscale NULL: Cartesian.
   const double* xscale = nullptr;
   int xper = 0;
+  // Grouped solve: per-RHS device tables of cx, cy, cz (NULL: the pointers above for all RHS).
+  const double* const* cx_rhs = nullptr;
+  const double* const* cy_rhs = nullptr;
+  const double* const* cz_rhs = nullptr;
   double sigma[kMaxRhs];
   // optional: the first workgroup clears these words (the refinement norms of the sweep the
   // residual starts), so no launch of its own is needed
@@ -163,5 +182,11 @@ hipError_t multi_axpy(double* w, const double* V, long long ldv, int nvec, const
 hipError_t axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st);
 // y[i] = a * x[i]   (x may equal y)
 hipError_t scale(double* y, const double* x, double a, long long n, hipStream_t st);
+
+// Writes n host-given pointers into device memory dst, stream-ordered (the values travel as
+// kernel arguments, kPtrBlock per launch), so a grouped solve's operand tables need no host
+// staging buffer and no synchronisation.
+constexpr int kPtrBlock = 240;
+hipError_t write_ptrs(const void* const* src, int n, const void** dst, hipStream_t st);
 
 }  // namespace helm

@@ -110,7 +110,9 @@ inline int kblock(Prec p) { return p == P_BF16 ? 32 : 16; }
 __device__ inline double column_shift(const EpiArgs& ep, long long n, int r) {
   const int ni = static_cast<int>(n);
   const int by = ni / ep.nx;
-  return ep.lamx[ni - by * ep.nx] + ep.lamy[by] + ep.sigma[r];
+  const double* lx = ep.lamx_rhs ? ep.lamx_rhs[r] : ep.lamx;
+  const double* ly = ep.lamy_rhs ? ep.lamy_rhs[r] : ep.lamy;
+  return lx[ni - by * ep.nx] + ly[by] + ep.sigma[r];
 }
 // Pointwise divide of eqs. 26-27 with the FP64 denominator lam_z(c) + shift; the exact zero
 // denominator of the all-Neumann null mode gives 0 (projection) or v (eq. 28: Lambda := 1).
@@ -206,6 +208,10 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   const long long total = S * Nn;
   const long long c0 = static_cast<long long>(blockIdx.x) * NT + wn * NB * 16;
   const int rb0 = wm * MB;
+  // grouped solve: the workgroup's columns lie inside one RHS, whose plan gives M and lambda_z
+  const long long rg = ep.msw_rhs ? static_cast<long long>(blockIdx.x) * NT / ep.span : 0;
+  const TC* __restrict__ Mp = ep.msw_rhs ? static_cast<const TC*>(ep.msw_rhs[rg]) : Msw;
+  [[maybe_unused]] const double* __restrict__ lamz = ep.lamz_rhs ? ep.lamz_rhs[rg] : ep.lamz;
   // FP64 divide: lambda_z of every output row staged in LDS before the main loop, so the
   // epilogue reads no global memory between its stores (FP32 keeps the registers of kPre below,
   // measured faster there)
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   constexpr int NLZ = kLds ? W * MB * 16 : 1;
   [[maybe_unused]] __shared__ double sh_lz[NLZ];
   if constexpr (kLds) {
-    for (int a = threadIdx.x; a < NLZ; a += blockDim.x) sh_lz[a] = a < K ? ep.lamz[a] : 1.0;
+    for (int a = threadIdx.x; a < NLZ; a += blockDim.x) sh_lz[a] = a < K ? lamz[a] : 1.0;
     __syncthreads();
   }
 
@@ -240,7 +246,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   auto load = [&](int kb, vec_t(&a)[MB], TC(&b)[NB][4]) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      a[mb] = *reinterpret_cast<const vec_t*>(Msw + ((static_cast<long long>(rb0 + mb) * KB + kb) * 64 + lane) * 4);
+      a[mb] = *reinterpret_cast<const vec_t*>(Mp + ((static_cast<long long>(rb0 + mb) * KB + kb) * 64 + lane) * 4);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = kb * 16 + 4 * g + s;
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
         for (int s = 0; s < 4; ++s) b_cur[nb][s] = b_nxt[nb][s];
     }
   }
-  // FP32 divide: eigenvalues of the lane's rows, all loaded before the first store (the vector-
+  // divide in the low-precision products: eigenvalues of the lane's rows, all loaded before the first store (the vector-
   // memory counter also counts stores: a load issued after a store would wait for it); the
   // widest entry (NB = 8, K <= 32) has no registers to spare and loads them at the store
   constexpr bool kPre = EPI == EPI_DIVIDE && !kLds && NB <= 4;
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = (rb0 + mb) * 16 + T::row(g, r);
-        lz[mb][r] = a < K ? ep.lamz[a] : 1.0;
+        lz[mb][r] = a < K ? lamz[a] : 1.0;
       }
   }
 #pragma unroll
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
           if constexpr (kLds) {
             Y[idx] = store_cvt<TC>(divide_den_sel(static_cast<double>(acc[mb][nb][r]), ep, sh_lz[a] + den_xy[nb]));
           } else {
-            const double lza = kPre ? lz[kPre ? mb : 0][r] : ep.lamz[a];
+            const double lza = kPre ? lz[kPre ? mb : 0][r] : lamz[a];
             Y[idx] = store_cvt<TC>(divide_den(static_cast<double>(acc[mb][nb][r]), ep, lza + den_xy[nb]));
           }
         } else {
@@ -325,6 +331,8 @@ __global__ __launch_bounds__(256, MINB) void k_right(const TC* __restrict__ Msw,
   const long long mwg = static_cast<long long>(blockIdx.x) * MT;
   const long long m0 = mwg + wm * MB * 16;
   const int cb0 = wn * NB;
+  // grouped solve: the workgroup's rows lie inside one RHS, whose plan gives M
+  const TC* __restrict__ Mp = ep.msw_rhs ? static_cast<const TC*>(ep.msw_rhs[mwg / ep.span]) : Msw;
 
   const TC* rowp[MB];
   bool rowok[MB];
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(256, MINB) void k_right(const TC* __restrict__ Msw,
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      b[nb] = *reinterpret_cast<const vec_t*>(Msw + ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 4);
+      b[nb] = *reinterpret_cast<const vec_t*>(Mp + ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 4);
   };
   if constexpr (PF) load(0, a_cur, b_cur);
   for (int kb = 0; kb < KB; ++kb) {

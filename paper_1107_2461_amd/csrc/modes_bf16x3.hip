@@ -44,12 +44,14 @@ hipError_t launch_rot(const bf16_t* Mp, long long piece, int KB, int K, const vo
 template <int CI, int RW>
 hipError_t launch_fit(const bf16_t* Mp, long long piece, int KB, int K, const void* Xv, bool x_f64, void* Y,
                       long long R, long long PQ, Epi epi, bool vec, const EpiArgs& ep, hipStream_t st) {
+  constexpr Cfg c = kCfgs[CI];
+  constexpr int MT = (4 / c.W) * RW * 16;
   if constexpr (RW > 1) {
-    constexpr Cfg c = kCfgs[CI];
-    constexpr int MT = (4 / c.W) * RW * 16;
-    if ((R * PQ + MT - 1) / MT < 512)
+    // (a grouped solve also halves it until a tile lies inside one RHS)
+    if ((R * PQ + MT - 1) / MT < 512 || !group_tiles_ok(ep, MT))
       return launch_fit<CI, RW / 2>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
   }
+  if (!group_tiles_ok(ep, MT)) return hipErrorInvalidValue;
   return launch_rot<CI, RW>(Mp, piece, KB, K, Xv, x_f64, Y, R, PQ, epi, vec, ep, st);
 }
 

@@ -34,7 +34,9 @@ hipError_t mode_left_f64(int ci, const void* Msw, int K, const void* X, void* Y,
     constexpr int CI = decltype(cic)::value;
     constexpr Cfg c = kCfgs[CI];
     constexpr int WN = 4 / c.W;
-    const int nb = narrow_nb(c.NB, WN, (S * Nn + 15) / 16);
+    int nb = narrow_nb(c.NB, WN, (S * Nn + 15) / 16);
+    while (nb > 1 && !group_tiles_ok(ep, static_cast<long long>(WN) * nb * 16)) nb = nb > 2 ? 2 : 1;
+    if (!group_tiles_ok(ep, static_cast<long long>(WN) * nb * 16)) return hipErrorInvalidValue;
     return with_nb(c.NB, nb, [&](auto nbc) -> hipError_t {
       constexpr int NB = decltype(nbc)::value == 0 ? c.NB : decltype(nbc)::value;
       constexpr int NT = WN * NB * 16;
@@ -62,7 +64,9 @@ hipError_t mode_right_f64(int ci, const void* Msw, int K, const void* X, void* Y
     constexpr int CI = decltype(cic)::value;
     constexpr Cfg c = kCfgs[CI];
     constexpr int WM = 4 / c.W;
-    const int nb = narrow_nb(c.NB, WM, (Mrows + 15) / 16);
+    int nb = narrow_nb(c.NB, WM, (Mrows + 15) / 16);
+    while (nb > 1 && !group_tiles_ok(ep, static_cast<long long>(WM) * nb * 16)) nb = nb > 2 ? 2 : 1;
+    if (!group_tiles_ok(ep, static_cast<long long>(WM) * nb * 16)) return hipErrorInvalidValue;
     return with_nb(c.NB, nb, [&](auto nbc) -> hipError_t {
       constexpr int RB = decltype(nbc)::value == 0 ? c.NB : decltype(nbc)::value;  // row blocks per wave
       constexpr int MT = WM * RB * 16;

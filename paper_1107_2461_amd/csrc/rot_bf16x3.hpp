@@ -64,11 +64,11 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   constexpr int CPT = (CHUNKS + 255) / 256;
   __shared__ u16x8 lds[2][3][RB * 64];    // [buffer][piece][row block * 64 + lane]
   // divide: lambda_x + lambda_y + sigma of every tile row and lambda_z of every output column,
-  // rounded to FP32 and staged before the main loop, so the epilogue waits on no global load
+  // in FP64, staged before the main loop, so the epilogue waits on no global load
   constexpr int NSH = EPI == EPI_DIVIDE ? MT : 4;
   constexpr int NLZ = EPI == EPI_DIVIDE ? W * NB * 16 : 4;
-  __shared__ __align__(16) float sh_shift[NSH];
-  __shared__ float sh_lamz[NLZ];
+  __shared__ __align__(16) double sh_shift[NSH];
+  __shared__ double sh_lamz[NLZ];
 
   const int tid = threadIdx.x;
   // the wave index is uniform: keep it (and every B-fragment base address) in scalar registers
@@ -79,6 +79,10 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   const long long mwg = static_cast<long long>(blockIdx.x) * MT;
   const int cb0 = wn * NB;
   const int rb0 = wm * MB;                // this wave's first row block inside the tile
+  // grouped solve: the tile's rows lie inside one RHS (span = PQ), whose plan gives M and the
+  // eigenvalues of the divide
+  const long long rg = ep.msw_rhs ? mwg / ep.span : 0;
+  const bf16_t* __restrict__ Mp = ep.msw_rhs ? static_cast<const bf16_t*>(ep.msw_rhs[rg]) : Msw;
 
   // producer assignment: chunk c -> row block c / 64, fragment lane c % 64
   const TIn* src[CPT];
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   auto load_b = [&](int kb, u16x8 (&b)[NB][3]) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const bf16_t* base = Msw + (static_cast<long long>(cb0 + nb) * KB + kb) * 512;
+      const bf16_t* base = Mp + (static_cast<long long>(cb0 + nb) * KB + kb) * 512;
       b[nb][0] = *reinterpret_cast<const u16x8*>(base + lane_off);
       b[nb][1] = *reinterpret_cast<const u16x8*>(base + piece + lane_off);
       b[nb][2] = *reinterpret_cast<const u16x8*>(base + 2 * piece + lane_off);
@@ -153,20 +157,18 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   u16x8 bcur[NB][3];
   load_tile(0, stage[0]);
   if constexpr (EPI == EPI_DIVIDE) {
-    // the parts of the denominator are summed in FP64 and each sum rounded once to FP32; an
-    // exact FP64 cancellation lamz + shift = 0 stays exact (the two roundings are negatives of
-    // each other), so the FP32 zero test sees the null mode
     const long long r0 = mwg / PQ;
     for (int i = tid; i < MT; i += 256) {
       const long long row = mwg + i;
-      float sv = 1.f;  // rows past the end: never stored
+      double sv = 1.0;  // rows past the end: never stored
       if (row < Mrows) {
         const long long rr = rhs_of_row(row, r0, PQ);
-        sv = static_cast<float>(ep.lamxy[row - rr * PQ] + ep.sigma[rr]);
+        sv = (ep.lamxy_rhs ? ep.lamxy_rhs[rr] : ep.lamxy)[row - rr * PQ] + ep.sigma[rr];
       }
       sh_shift[i] = sv;
     }
-    for (int a = tid; a < NLZ; a += 256) sh_lamz[a] = a < K ? static_cast<float>(ep.lamz[a]) : 1.f;
+    const double* __restrict__ lamz = ep.lamz_rhs ? ep.lamz_rhs[rg] : ep.lamz;
+    for (int a = tid; a < NLZ; a += 256) sh_lamz[a] = a < K ? lamz[a] : 1.0;
   }
   store_tile(0, stage[0]);
 #pragma unroll
@@ -207,21 +209,19 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
 
   // epilogue: lane holds rows m = mwg + (rb0 + mb)*16 + 4g + t (t < 4), column a = (cb0 + nb)*16 + l16
   const long long r_lo = mwg / PQ;
-  [[maybe_unused]] float shift[EPI == EPI_DIVIDE ? MB : 1][4];
-  [[maybe_unused]] float lamz_c[EPI == EPI_DIVIDE ? NB : 1];
+  [[maybe_unused]] double lamz_c[EPI == EPI_DIVIDE ? NB : 1];
   if constexpr (EPI == EPI_DIVIDE) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const f4 s4 = *reinterpret_cast<const f4*>(&sh_shift[(rb0 + mb) * 16 + 4 * g]);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) shift[mb][t] = s4[t];
-    }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) lamz_c[nb] = sh_lamz[(cb0 + nb) * 16 + l16];
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     const long long mq = mwg + (rb0 + mb) * 16 + 4 * g;  // first of the lane's four rows
+    [[maybe_unused]] double shift[4];
+    if constexpr (EPI == EPI_DIVIDE) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) shift[t] = sh_shift[(rb0 + mb) * 16 + 4 * g + t];
+    }
     long long rr[4], pq[4];
     if (PQ >= MT) {  // at most one RHS boundary inside the tile: branch-free split
       const long long o = mq - r_lo * PQ;
@@ -259,11 +259,13 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
         float* Y = static_cast<float*>(Yv);
         f4 v = acc[mb][nb];
         if constexpr (EPI == EPI_DIVIDE) {
-          // FP32 divide by the hardware reciprocal (1 ulp, at the precision of the data)
+          // eqs. 26-28: the denominator summed in FP64 and rounded once to FP32 (an exact FP64
+          // zero, the Neumann null mode, is tested before rounding), then the FP32 hardware
+          // reciprocal (1 ulp): at the precision of the FP32 data it divides
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const float d = lamz_c[nb] + shift[mb][t];
-            v[t] = d == 0.f ? (ep.eq28 ? v[t] : 0.f) : v[t] * __builtin_amdgcn_rcpf(d);
+            const double d = lamz_c[nb] + shift[t];
+            v[t] = d == 0.0 ? (ep.eq28 ? v[t] : 0.f) : v[t] * __builtin_amdgcn_rcpf(static_cast<float>(d));
           }
         }
         if (full) {

@@ -27,6 +27,7 @@
 #include "../../include/helm.h"
 #include "alloc.hpp"
 #include "kernels.hpp"
+#include "solve_impl.hpp"
 
 namespace {
 
@@ -129,11 +130,18 @@ struct Request {
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Footprint of one multi-RHS solve of `total` right-hand sides on plan p with staging for f and
-// u, or 0 when the size cannot be had.
-inline size_t batch_foot(helm_plan* p, int total, long long npts) {
+// Workspace of a batch of `total` right-hand sides led by plan p: a grouped solve's (the plan's
+// own layout plus the per-RHS operand table), which also serves a batch on p alone; 0 when the
+// size cannot be had.
+inline size_t batch_ws(helm_plan* p, int total) {
   size_t ws = 0;
-  if (helm_workspace_size(p, total, &ws) != HELM_OK) return 0;
+  if (helm_group_workspace_size(&p, 1, &total, &ws) != HELM_OK) return 0;
+  return ws;
+}
+// Footprint of one batch solve with staging for f and u, or 0 when the size cannot be had.
+inline size_t batch_foot(helm_plan* p, int total, long long npts) {
+  const size_t ws = batch_ws(p, total);
+  if (ws == 0) return 0;
   return align256(ws) + 2 * static_cast<size_t>(total) * static_cast<size_t>(npts) * sizeof(double);
 }
 
@@ -213,16 +221,19 @@ struct helm_server {
     }
   }
 
-  // Pull queued requests on r's plan into r's solve while the right-hand sides fit one solve
-  // (64) and the grown footprint fits the budget.  Riders pass requests queued before them only
-  // while the head of the queue has waited less than max_bypass (or is itself the rider).
+  // Pull queued requests into r's solve while the right-hand sides fit one solve (64) and the
+  // grown footprint fits the budget: requests on r's plan, and requests on other grids of r's
+  // shape that a grouped solve can take (each multiplied by its own plan's eigenbases).  Riders
+  // pass requests queued before them only while the head of the queue has waited less than
+  // max_bypass (or is itself the rider).
   void add_riders(Request* r, size_t largest) {
     int total = r->nrhs;
     const double t = now();
     for (size_t j = 0; j < queue.size();) {
       Request& q = *queue[j];
       const bool head_ok = j == 0 || t - queue.front()->t_submit < max_bypass;
-      if (q.plan != r->plan || total + q.nrhs > 64 || !head_ok) {
+      const bool joins = q.plan == r->plan || helm::plans_groupable(r->plan.get(), q.plan.get());
+      if (!joins || total + q.nrhs > 64 || !head_ok) {
         ++j;
         continue;
       }
@@ -236,9 +247,10 @@ struct helm_server {
     }
   }
 
-  // One request alone, or a batch as one multi-RHS solve through staging buffers after the
-  // solve's workspace; a batch the solver refuses (e.g. mixed singular and regular shifts on an
-  // all-Neumann plan) is solved request by request.  Returns a status per request.
+  // One request alone, or a batch as one multi-RHS (one plan) or grouped (several grids of one
+  // shape) solve through staging buffers after the solve's workspace; a batch the solver
+  // refuses (e.g. mixed singular and regular shifts on an all-Neumann plan) is solved request
+  // by request.  Returns a status per request.
   std::vector<helm_status> run(Request& r, Slot& s, helm_info& info) {
     std::vector<Request*> reqs{&r};
     for (auto& q : r.riders) reqs.push_back(q.get());
@@ -261,12 +273,18 @@ struct helm_server {
     }
     int total = 0;
     std::vector<double> sig;
+    std::vector<helm_plan*> plans;
+    std::vector<int> counts;
+    bool one_plan = true;
     for (Request* q : reqs) {
       total += q->nrhs;
       sig.insert(sig.end(), q->sigma.begin(), q->sigma.end());
+      plans.push_back(q->plan.get());
+      counts.push_back(q->nrhs);
+      one_plan = one_plan && q->plan == r.plan;
     }
-    size_t ws = 0;
-    helm_status st = helm_workspace_size(r.plan.get(), total, &ws);
+    const size_t ws = batch_ws(r.plan.get(), total);
+    helm_status st = ws ? HELM_OK : HELM_EINVAL;
     double* F = reinterpret_cast<double*>(static_cast<char*>(s.ws) + align256(ws));
     double* U = F + static_cast<size_t>(total) * r.npts;
     const size_t per = static_cast<size_t>(r.npts) * sizeof(double);
@@ -277,7 +295,10 @@ struct helm_server {
         st = HELM_EDEVICE;
       o += q->nrhs;
     }
-    if (st == HELM_OK) st = helm_solve(r.plan.get(), F, U, total, sig.data(), s.ws, s.stream, &info);
+    if (st == HELM_OK)
+      st = one_plan ? helm_solve(r.plan.get(), F, U, total, sig.data(), s.ws, s.stream, &info)
+                    : helm_solve_group(plans.data(), static_cast<int>(plans.size()), counts.data(), F, U, sig.data(),
+                                       s.ws, s.stream, &info);
     if (st == HELM_EINVAL) {
       for (size_t i = 0; i < reqs.size(); ++i) out[i] = one(*reqs[i]);
       return out;

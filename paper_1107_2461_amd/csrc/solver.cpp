@@ -646,7 +646,8 @@ hipError_t timed(const helm_plan* p, int stage, hipStream_t st, F&& launch) {
 // `out` with epilogue epi_last (STORE in pr, or ACCUM into FP64 u).
 hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, void* b2, void* out, Epi epi_last,
                         int nrhs, const double* sig, unsigned long long* norms, int accum_zero, hipStream_t st,
-                        bool in_f64 = false, bool u0_f32 = false, const float* u0 = nullptr) {
+                        bool in_f64 = false, bool u0_f32 = false, const float* u0 = nullptr,
+                        const GroupTabs* grp = nullptr) {
   const DevAxis& X = *p->ax[0];
   const DevAxis& Y = *p->ax[1];
   const DevAxis& Z = *p->ax[2];
@@ -662,29 +663,44 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   ep.rows_per_rhs = ny * nz;
   ep.accum_zero = accum_zero;
   for (int r = 0; r < nrhs; ++r) ep.sigma[r] = sig[r];
+  if (grp) {
+    ep.lamx_rhs = grp->lam[0];
+    ep.lamy_rhs = grp->lam[1];
+    ep.lamz_rhs = grp->lam[2];
+    ep.lamxy_rhs = grp->lamxy;
+  }
+  // the arguments of one stage: in a grouped solve, the per-RHS operand of (axis, direction)
+  // and the extent of one RHS in the stage's tiled dimension
+  auto G = [&](int axis, int dir, long long span) -> const EpiArgs& {
+    if (grp) {
+      ep.msw_rhs = grp->msw[axis][dir];
+      ep.span = span;
+    }
+    return ep;
+  };
   hipError_t e;
   if (pr == P_BF16X3) {
     // rotating layout: [k][j][i] -> [a][k][j] -> [b][a][k] -> [c][b][a] -> [i][c][b] -> [j][i][c] -> [k][j][i]
     float* f1 = static_cast<float*>(b1);
     float* f2 = static_cast<float*>(b2);
     if ((e = timed(p, in_f64 ? HELM_STAGE_X_FWD_RHS : HELM_STAGE_X_FWD, st, [&] {
-           return mode_rot(X.sw3[0], nx, in, in_f64, f1, nrhs, ny * nz, EPI_STORE, ep, st);
+           return mode_rot(X.sw3[0], nx, in, in_f64, f1, nrhs, ny * nz, EPI_STORE, G(0, 0, ny * nz), st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
-           return mode_rot(Y.sw3[0], ny, f1, false, f2, nrhs, nz * nx, EPI_STORE, ep, st);
+           return mode_rot(Y.sw3[0], ny, f1, false, f2, nrhs, nz * nx, EPI_STORE, G(1, 0, nz * nx), st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_Z_FWD_DIV, st, [&] {
-           return mode_rot(Z.sw3[0], nz, f2, false, f1, nrhs, nx * ny, EPI_DIVIDE, ep, st);
+           return mode_rot(Z.sw3[0], nz, f2, false, f1, nrhs, nx * ny, EPI_DIVIDE, G(2, 0, nx * ny), st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_X_INV, st, [&] {
-           return mode_rot(X.sw3[1], nx, f1, false, f2, nrhs, nz * ny, EPI_STORE, ep, st);
+           return mode_rot(X.sw3[1], nx, f1, false, f2, nrhs, nz * ny, EPI_STORE, G(0, 1, nz * ny), st);
          })) != hipSuccess)
       return e;
     if ((e = timed(p, HELM_STAGE_Y_INV, st, [&] {
-           return mode_rot(Y.sw3[1], ny, f2, false, f1, nrhs, nx * nz, EPI_STORE, ep, st);
+           return mode_rot(Y.sw3[1], ny, f2, false, f1, nrhs, nx * nz, EPI_STORE, G(1, 1, nx * nz), st);
          })) != hipSuccess)
       return e;
     if (epi_last != EPI_ACCUM) return hipErrorInvalidValue;
@@ -693,13 +709,14 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
       // (u0_f32) when refinement follows: its error (~1e-7) is far above FP32 rounding, and the
       // FP64 residual of the FP32 values is exact, so the next sweep corrects both
       return timed(p, HELM_STAGE_Z_INV_U, st, [&] {
-        return mode_rot(Z.sw3[1], nz, f1, false, out, nrhs, ny * nx, u0_f32 ? EPI_STORE : EPI_STORE_F64, ep, st);
+        return mode_rot(Z.sw3[1], nz, f1, false, out, nrhs, ny * nx, u0_f32 ? EPI_STORE : EPI_STORE_F64, G(2, 1, ny * nx),
+                        st);
       });
     }
     // a correction lands in FP32 (natural layout) and is added to u by a streaming kernel
     // that also takes the norms the refinement loop stops on
     if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
-           return mode_rot(Z.sw3[1], nz, f1, false, f2, nrhs, ny * nx, EPI_STORE, ep, st);
+           return mode_rot(Z.sw3[1], nz, f1, false, f2, nrhs, ny * nx, EPI_STORE, G(2, 1, ny * nx), st);
          })) != hipSuccess)
       return e;
     // u = u0 + du when the previous iterate is the FP32 first solve, else u += du
@@ -737,43 +754,48 @@ hipError_t tpf_products(const helm_plan* p, Prec pr, const void* in, void* b1, v
   // forward: E_x^{-1}, E_y^{-1}, E_z^{-1} + divide
   if ((e = timed(p, HELM_STAGE_X_FWD, st, [&] {
          if (fx) return fft_axis(static_cast<const double*>(in), static_cast<double*>(b1), X.fft[0], lx, EPI_STORE, ep, st);
-         return mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, ep, st);
+         return mode_right(pr, X.sw[ip][0], nx, in, pr, b1, pr, nrhs * ny * nz, EPI_STORE, G(0, 0, ny * nz), st);
        })) != hipSuccess)
     return e;
   if ((e = timed(p, HELM_STAGE_Y_FWD, st, [&] {
          if (fy) return fft_axis(static_cast<const double*>(b1), static_cast<double*>(b2), Y.fft[0], ly, EPI_STORE, ep, st);
-         return mode_left(pr, Y.sw[ip][0], ny, b1, pr, b2, pr, nrhs * nz, nx, EPI_STORE, ep, st);
+         return mode_left(pr, Y.sw[ip][0], ny, b1, pr, b2, pr, nrhs * nz, nx, EPI_STORE, G(1, 0, nz * nx), st);
        })) != hipSuccess)
     return e;
   if ((e = timed(p, HELM_STAGE_Z_FWD_DIV, st, [&] {
          if (fz) return fft_axis(static_cast<const double*>(b2), static_cast<double*>(b1), Z.fft[0], lz, EPI_DIVIDE, ep, st);
-         return mode_left(pr, Z.sw[ip][0], nz, b2, pr, b1, pr, nrhs, nx * ny, EPI_DIVIDE, ep, st);
+         return mode_left(pr, Z.sw[ip][0], nz, b2, pr, b1, pr, nrhs, nx * ny, EPI_DIVIDE, G(2, 0, nx * ny), st);
        })) != hipSuccess)
     return e;
   // inverse: E_z, E_y, E_x
   if ((e = timed(p, HELM_STAGE_Z_INV, st, [&] {
          if (fz) return fft_axis(static_cast<const double*>(b1), static_cast<double*>(b2), Z.fft[1], lz, EPI_STORE, ep, st);
-         return mode_left(pr, Z.sw[ip][1], nz, b1, pr, b2, pr, nrhs, nx * ny, EPI_STORE, ep, st);
+         return mode_left(pr, Z.sw[ip][1], nz, b1, pr, b2, pr, nrhs, nx * ny, EPI_STORE, G(2, 1, nx * ny), st);
        })) != hipSuccess)
     return e;
   if ((e = timed(p, HELM_STAGE_Y_INV, st, [&] {
          if (fy) return fft_axis(static_cast<const double*>(b2), static_cast<double*>(b1), Y.fft[1], ly, EPI_STORE, ep, st);
-         return mode_left(pr, Y.sw[ip][1], ny, b2, pr, b1, pr, nrhs * nz, nx, EPI_STORE, ep, st);
+         return mode_left(pr, Y.sw[ip][1], ny, b2, pr, b1, pr, nrhs * nz, nx, EPI_STORE, G(1, 1, nz * nx), st);
        })) != hipSuccess)
     return e;
   const Prec tout = epi_last == EPI_ACCUM ? P_F64 : pr;
   return timed(p, HELM_STAGE_X_INV, st, [&] {
     if (fx && epi_last == EPI_STORE)
       return fft_axis(static_cast<const double*>(b1), static_cast<double*>(out), X.fft[1], lx, EPI_STORE, ep, st);
-    return mode_right(pr, X.sw[ip][1], nx, b1, pr, out, tout, nrhs * ny * nz, epi_last, ep, st);
+    return mode_right(pr, X.sw[ip][1], nx, b1, pr, out, tout, nrhs * ny * nz, epi_last, G(0, 1, ny * nz), st);
   });
 }
 
-StencilArgs stencil_args(const helm_plan* p, int nrhs, const double* sig) {
+StencilArgs stencil_args(const helm_plan* p, int nrhs, const double* sig, const GroupTabs* grp = nullptr) {
   StencilArgs a;
   a.cx = p->ax[0]->coef;
   a.cy = p->ax[1]->coef;
   a.cz = p->ax[2]->coef;
+  if (grp) {
+    a.cx_rhs = grp->coef[0];
+    a.cy_rhs = grp->coef[1];
+    a.cz_rhs = grp->coef[2];
+  }
   a.nx = p->m[0];
   a.ny = p->m[1];
   a.nz = p->m[2];
@@ -807,12 +829,121 @@ extern "C" helm_status helm_solve(helm_plan* p, const double* f, double* u, int 
 
 int helm::plan_device(const helm_plan* p) { return p ? p->device : -1; }
 
+// ---------------------------------------------------------------- grouped solves
+namespace {
+
+// Pointer slots of a grouped solve's device table: msw[axis][dir] (6), lam[axis] (3), lamxy,
+// coef[axis] (3), kMaxRhs entries each.
+constexpr int kGroupSlots = 13;
+constexpr size_t kGroupTabBytes = static_cast<size_t>(kGroupSlots) * kMaxRhs * sizeof(void*);
+
+// Checks that the plans can share one solve and returns the total right-hand-side count.
+helm_status group_check(helm_plan* const* plans, int nplans, const int* nrhs, int* total) {
+  if (!plans || !nrhs || nplans < 1 || !total) return HELM_EINVAL;
+  const helm_plan* p0 = plans[0];
+  if (!p0) return HELM_EINVAL;
+  int t = 0;
+  for (int i = 0; i < nplans; ++i) {
+    const helm_plan* q = plans[i];
+    if (!q || nrhs[i] < 1) return HELM_EINVAL;
+    t += nrhs[i];
+    if (t > kMaxRhs) return HELM_EINVAL;
+    if (q->cyl || q->opts.method != HELM_TPF || (q->prec() != P_F64 && q->prec() != P_BF16X3)) return HELM_EINVAL;
+    if (q->device != p0->device || q->opts.precision != p0->opts.precision || q->opts.ir_tol != p0->opts.ir_tol ||
+        q->opts.max_sweeps != p0->opts.max_sweeps || q->opts.null_mode != p0->opts.null_mode)
+      return HELM_EINVAL;
+    for (int d = 0; d < 3; ++d)
+      if (q->m[d] != p0->m[d]) return HELM_EINVAL;
+  }
+  *total = t;
+  return HELM_OK;
+}
+
+size_t group_tab_offset(const helm_plan* p0, int total) {
+  size_t bytes = 0, a, b, c;
+  workspace_layout(p0, total, &bytes, &a, &b, &c);
+  return align_up(bytes, 256);
+}
+
+}  // namespace
+
+bool helm::plans_groupable(const helm_plan* a, const helm_plan* b) {
+  if (!a || !b) return false;
+  helm_plan* const pl[2] = {const_cast<helm_plan*>(a), const_cast<helm_plan*>(b)};
+  const int n[2] = {1, 1};
+  int total = 0;
+  if (group_check(pl, 2, n, &total) != HELM_OK) return false;
+  const long long nx = a->m[0], ny = a->m[1], nz = a->m[2];
+  return (ny * nz) % 512 == 0 && (nz * nx) % 512 == 0 && (nx * ny) % 512 == 0;
+}
+
+extern "C" helm_status helm_group_workspace_size(helm_plan* const* plans, int nplans, const int* nrhs,
+                                                 size_t* bytes) {
+  int total = 0;
+  if (!bytes) return HELM_EINVAL;
+  const helm_status s = group_check(plans, nplans, nrhs, &total);
+  if (s != HELM_OK) return s;
+  *bytes = group_tab_offset(plans[0], total) + kGroupTabBytes;
+  return HELM_OK;
+}
+
+extern "C" helm_status helm_solve_group(helm_plan* const* plans, int nplans, const int* nrhs, const double* f,
+                                        double* u, const double* sigma, void* ws, void* stream, helm_info* info) {
+  int total = 0;
+  helm_status s = group_check(plans, nplans, nrhs, &total);
+  if (s != HELM_OK) return s;
+  if (!f || !u || !ws) return HELM_EINVAL;
+  helm_plan* p0 = plans[0];
+  std::vector<double> sig(total);
+  std::vector<const helm_plan*> owner(total);
+  bool one_plan = true;
+  for (int i = 0, r = 0; i < nplans; ++i) {
+    one_plan = one_plan && plans[i] == p0;
+    for (int k = 0; k < nrhs[i]; ++k, ++r) {
+      sig[r] = sigma ? sigma[r] : plans[i]->sigma;
+      owner[r] = plans[i];
+    }
+  }
+  // one plan: an ordinary multi-RHS solve
+  if (one_plan) return helm::solve_impl(p0, f, u, total, sig.data(), ws, stream, info, false);
+  // the per-RHS table, written into the workspace by the stream itself
+  std::vector<const void*> tab(static_cast<size_t>(kGroupSlots) * kMaxRhs, nullptr);
+  const int ip = static_cast<int>(p0->prec());
+  for (int r = 0; r < total; ++r) {
+    const helm_plan* q = owner[r];
+    for (int a = 0; a < 3; ++a) {
+      const DevAxis& A = *q->ax[a];
+      for (int d = 0; d < 2; ++d)
+        tab[(2 * a + d) * kMaxRhs + r] = ip == P_BF16X3 ? A.sw3[d] : A.sw[ip][d];
+      tab[(6 + a) * kMaxRhs + r] = A.lam;
+      tab[(10 + a) * kMaxRhs + r] = A.coef;
+    }
+    tab[9 * kMaxRhs + r] = q->lamxy ? q->lamxy->p : nullptr;
+    if (ip == P_BF16X3 && !q->lamxy) return HELM_EINVAL;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return HELM_EINVAL;
+  const void** dtab =
+      reinterpret_cast<const void**>(static_cast<unsigned char*>(ws) + group_tab_offset(p0, total));
+  DeviceGuard dg(p0->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (helm::write_ptrs(tab.data(), static_cast<int>(tab.size()), dtab, st) != hipSuccess) return HELM_EDEVICE;
+  helm::GroupTabs g;
+  for (int a = 0; a < 3; ++a) {
+    for (int d = 0; d < 2; ++d) g.msw[a][d] = dtab + (2 * a + d) * kMaxRhs;
+    g.lam[a] = reinterpret_cast<const double* const*>(dtab + (6 + a) * kMaxRhs);
+    g.coef[a] = reinterpret_cast<const double* const*>(dtab + (10 + a) * kMaxRhs);
+  }
+  g.lamxy = reinterpret_cast<const double* const*>(dtab + 9 * kMaxRhs);
+  g.rhs_plan = owner.data();
+  return helm::solve_impl(p0, f, u, total, sig.data(), ws, stream, info, false, &g);
+}
+
 // The solve sequence shared by helm_solve and helm_solve_noalloc.  noalloc: the call must not
 // allocate anything, so the two paths that create objects on demand are refused (EINVAL):
 // adaptive refinement (its norms are read back through pinned host memory and a per-thread
 // event) and stage timing (its events are created lazily).
 helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs, const double* sigma_per_rhs,
-                             void* ws, void* stream, helm_info* info, bool noalloc) {
+                             void* ws, void* stream, helm_info* info, bool noalloc, const GroupTabs* grp) {
   if (!p || !f || !u || nrhs < 1 || nrhs > kMaxRhs) return HELM_EINVAL;
   if (p->refined() && f == u) return HELM_EINVAL;
   if (noalloc && (p->prof.on || (p->refined() && p->opts.ir_tol != 0.0))) return HELM_EINVAL;
@@ -823,8 +954,9 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
   for (int r = 0; r < nrhs; ++r) {
     sig[r] = sigma_per_rhs ? sigma_per_rhs[r] : p->sigma;
     if (!std::isfinite(sig[r])) return HELM_EINVAL;
+    const helm_plan* pr_r = grp ? grp->rhs_plan[r] : p;  // the plan that owns RHS r
     if (p->cyl && sig[r] < 0.0) return HELM_EINVAL;
-    if (!p->cyl && sig[r] != p->sigma && has_zero_denominator(p, sig[r])) return HELM_ESINGULAR;
+    if (!p->cyl && sig[r] != pr_r->sigma && has_zero_denominator(pr_r, sig[r])) return HELM_ESINGULAR;
   }
   DeviceGuard dg(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -837,9 +969,12 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
   // no refinement sweep can see (H 1 = 0); it is removed at the end with an FP64
   // volume-weighted mean.
   unsigned long long null_mask = 0;
-  if (p->all_neumann && p->opts.null_mode == HELM_NULL_PROJECT)
-    for (int r = 0; r < nrhs; ++r)
-      if (sig[r] == 0.0) null_mask |= 1ull << r;
+  for (int r = 0; r < nrhs; ++r) {
+    const helm_plan* pr_r = grp ? grp->rhs_plan[r] : p;
+    if (pr_r->all_neumann && p->opts.null_mode == HELM_NULL_PROJECT && sig[r] == 0.0) null_mask |= 1ull << r;
+  }
+  // a grouped low-precision solve has no per-plan volume tables for the final projection
+  if (grp && null_mask && pr != P_F64) return HELM_EINVAL;
   auto project_null = [&]() -> hipError_t {
     if (!null_mask) return hipSuccess;
     double vs = 1.0;
@@ -869,8 +1004,9 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
     const long long nx = p->m[0], ny = p->m[1], nz = p->m[2];
     if (!p->thomas()) {  // TPF, and HELM_FFT (TPF with fast transforms on uniform axes)
       // f -> W -> u -> W -> u -> W -> u  (u may alias f: f is consumed by the first product)
-      e = tpf_products(p, P_F64, f, W, u, u, EPI_STORE, nrhs, sig, nullptr, 0, st);
+      e = tpf_products(p, P_F64, f, W, u, u, EPI_STORE, nrhs, sig, nullptr, 0, st, false, false, nullptr, grp);
     } else {
+      if (grp) return HELM_EINVAL;
       EpiArgs ep;
       ep.nx = static_cast<int>(nx);
       ThomasArgs ta;
@@ -925,7 +1061,8 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
   void* L1 = w + off_a;
   void* L2 = w + off_b;
   unsigned long long* norms = reinterpret_cast<unsigned long long*>(w + off_n);
-  const StencilArgs sa = stencil_args(p, nrhs, sig);
+  if (grp && pr != P_BF16X3) return HELM_EINVAL;
+  const StencilArgs sa = stencil_args(p, nrhs, sig, grp);
   const Prec store = pr == P_BF16X3 ? P_F32 : pr;  // storage type of the low-precision fields
   // Sweep 0: L1 = low(f) (the residual of u = 0), u = M^{-1} L1.  Its norms are not read: the
   // first correction is measured against u itself.
@@ -936,7 +1073,7 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
   if (pr == P_BF16X3) {  // the first product reads f in FP64 directly
     if (e == hipSuccess)
       e = tpf_products(p, pr, f, L2, L1, U0 ? static_cast<void*>(U0) : static_cast<void*>(u), EPI_ACCUM, nrhs, sig,
-                       norms, 1, st, true, U0 != nullptr);
+                       norms, 1, st, true, U0 != nullptr, nullptr, grp);
   } else {
     if (e == hipSuccess)
       e = timed(p, HELM_STAGE_CONVERT, st, [&] { return stencil(2, nullptr, f, L1, store, sa, st); });
@@ -963,7 +1100,8 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
       e = timed(p, HELM_STAGE_RESIDUAL, st, [&] {
         return u0 ? stencil_u32(1, u0, f, L1, store, sz, st) : stencil(1, u, f, L1, store, sz, st);
       });
-    if (e == hipSuccess) e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st, false, false, u0);
+    if (e == hipSuccess)
+      e = tpf_products(p, pr, L1, L2, L1, u, EPI_ACCUM, nrhs, sig, norms, 0, st, false, false, u0, grp);
     if (e == hipSuccess && !fixed)
       e = hipMemcpyAsync(hn->p, norms, 2 * nrhs * kNormStripes * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st);
