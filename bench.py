@@ -1192,7 +1192,7 @@ def main():
     roofline = dict(kernel=dom, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
                     frac=d["frac"], traffic=committed_traffic(b["precision"], dom), avg_us=d["avg_us"],
                     algorithmic_bytes=d.get("algorithmic_bytes"), algorithmic_flops=d.get("algorithmic_flops"))
-    if "algorithmic_tflops" in d:
+    if "algorithmic_tflops" in d and "issued_flops_factor" in d:
         # the contraction's rate beside the bound: algorithmic flops, and the flops the matrix cores
         # issue (six per algorithmic one for split BF16), each against the contraction dtype's peak
         pk = MFMA_PEAK_TFLOPS[b["precision"]]

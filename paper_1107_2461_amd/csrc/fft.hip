@@ -31,7 +31,7 @@ __device__ inline d2 cmul(d2 a, d2 b) { return d2{a.x * b.x - a.y * b.y, a.x * b
 __device__ inline d2 mul_i(d2 a) { return d2{-a.y, a.x}; }  // i * a
 
 // 4-point DFT with the positive exponent (i^{pq})
-__device__ inline void dft4(d2& v0, d2& v1, d2& v2, d2& v3) {
+__device__ __attribute__((always_inline)) inline void dft4(d2& v0, d2& v1, d2& v2, d2& v3) {
   const d2 s02 = v0 + v2, d02 = v0 - v2, s13 = v1 + v3, d13 = mul_i(v1 - v3);
   v0 = s02 + s13;
   v2 = s02 - s13;
@@ -43,7 +43,7 @@ __device__ inline void dft4(d2& v0, d2& v1, d2& v2, d2& v3) {
 // radices of the earlier stages.  Every thread gathers its butterflies, twiddles them, forms
 // the R-point DFTs in registers, waits for the whole workgroup, then scatters.
 template <int R>
-__device__ inline void stage(d2* buf, int L, int B, int Ns, const d2* __restrict__ W) {
+__device__ __attribute__((always_inline)) inline void stage(d2* buf, int L, int B, int Ns, const d2* __restrict__ W) {
   constexpr int U = (kFftBuf / R + 255) / 256;
   const int nb = L / R;
   const int total = B * nb;
@@ -122,6 +122,7 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
                                              FftLines ln, EpiArgs ep) {
   extern __shared__ d2 buf[];  // B lines of L complex values
   __shared__ long long lbase[kFftMaxLines];
+  __shared__ double lshift[EPI == EPI_DIVIDE ? kFftMaxLines : 1];
   const int L = t.L, N = t.N;
   const int B = t.lines;
   const long long line0 = static_cast<long long>(blockIdx.x) * B;
@@ -131,6 +132,8 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
     const long long a0 = line % ln.n0, rest = line / ln.n0;
     const long long a1 = rest % ln.n1, a2 = rest / ln.n1;
     lbase[b] = a2 * ln.t2 + a1 * ln.t1 + a0 * ln.t0;
+    // z-forward: the line is (rhs, y mode, x mode); its part of the eq. 26-27 denominator
+    if constexpr (EPI == EPI_DIVIDE) lshift[b] = ep.lamx[a0] + ep.lamy[a1] + ep.sigma[a2];
   }
   __syncthreads();
   const d2* pre = reinterpret_cast<const d2*>(t.pre);
@@ -190,15 +193,7 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
     const d2 Y = buf[fft_lds_index(b * L + p)];
     const d2 ps = post[p];
     double v = ps.x * Y.x - ps.y * Y.y;
-    if constexpr (EPI == EPI_DIVIDE) {
-      // z-forward: the line is (rhs, y mode, x mode), p is the z mode (eqs. 26-28)
-      const long long line = line0 + b;
-      const int a = static_cast<int>(line % ln.n0);
-      const long long rest = line / ln.n0;
-      const int bb = static_cast<int>(rest % ln.n1);
-      const int rr = static_cast<int>(rest / ln.n1);
-      v = divide_den(v, ep, ep.lamz[p] + (ep.lamx[a] + ep.lamy[bb] + ep.sigma[rr]));
-    }
+    if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);  // p: the z mode (eqs. 26-28)
     out[lbase[b] + p * ln.se] = v;
   }
 }
@@ -211,7 +206,7 @@ constexpr int pow2_lines() {
 }
 
 template <int R, int L, int Ns>
-__device__ inline void stage_c(d2* buf, const d2* __restrict__ W) {
+__device__ __attribute__((always_inline)) inline void stage_c(d2* buf, const d2* __restrict__ W) {
   constexpr int B = pow2_lines<L>();
   constexpr int nb = L / R;
   constexpr int total = B * nb;
@@ -271,7 +266,7 @@ __device__ inline void stage_c(d2* buf, const d2* __restrict__ W) {
 
 // radix 8 while at least 8 remain, then one radix-4 or radix-2 stage
 template <int L, int Ns>
-__device__ inline void stages_pow2(d2* buf, const d2* __restrict__ W) {
+__device__ __attribute__((always_inline)) inline void stages_pow2(d2* buf, const d2* __restrict__ W) {
   constexpr int rem = L / Ns;
   if constexpr (rem >= 8) {
     stage_c<8, L, Ns>(buf, W);
@@ -289,6 +284,7 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
   constexpr int B = pow2_lines<L>();
   __shared__ d2 buf[fft_lds_index(B * L - 1) + 1];
   __shared__ long long lbase[B];
+  __shared__ double lshift[EPI == EPI_DIVIDE ? B : 1];
   const int N = t.N;
   const long long line0 = static_cast<long long>(blockIdx.x) * B;
   const int nl = static_cast<int>(min<long long>(B, ln.nlines - line0));
@@ -297,6 +293,7 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
     const long long a0 = line % ln.n0, rest = line / ln.n0;
     const long long a1 = rest % ln.n1, a2 = rest / ln.n1;
     lbase[threadIdx.x] = a2 * ln.t2 + a1 * ln.t1 + a0 * ln.t0;
+    if constexpr (EPI == EPI_DIVIDE) lshift[threadIdx.x] = ep.lamx[a0] + ep.lamy[a1] + ep.sigma[a2];
   }
   __syncthreads();
   const d2* pre = reinterpret_cast<const d2*>(t.pre);
@@ -331,14 +328,7 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
     const d2 Y = buf[fft_lds_index(b * L + p)];
     const d2 ps = post[p];
     double v = ps.x * Y.x - ps.y * Y.y;
-    if constexpr (EPI == EPI_DIVIDE) {
-      const long long line = line0 + b;
-      const int a = static_cast<int>(line % ln.n0);
-      const long long rest = line / ln.n0;
-      const int bb = static_cast<int>(rest % ln.n1);
-      const int rr = static_cast<int>(rest / ln.n1);
-      v = divide_den(v, ep, ep.lamz[p] + (ep.lamx[a] + ep.lamy[bb] + ep.sigma[rr]));
-    }
+    if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
     out[lbase[b] + p * ln.se] = v;
   }
 }
