@@ -393,9 +393,9 @@ __global__ __launch_bounds__(256) void k_stencil(const TU* __restrict__ u,
   const int ic = iok ? i : a.nx - 1;  // lanes past the end load a valid column, store nothing
   const long long plane = static_cast<long long>(a.nx) * a.ny;
   const long long rbase = static_cast<long long>(r) * plane * a.nz;
-  const double* __restrict__ cx = a.cx_rhs ? a.cx_rhs[r] : a.cx;
-  const double* __restrict__ cy = a.cy_rhs ? a.cy_rhs[r] : a.cy;
-  const double* __restrict__ cz = a.cz_rhs ? a.cz_rhs[r] : a.cz;
+  const gptr_t<double> cx = rhs_ptr(a.cx_rhs, r, a.cx);
+  const gptr_t<double> cy = rhs_ptr(a.cy_rhs, r, a.cy);
+  const gptr_t<double> cz = rhs_ptr(a.cz_rhs, r, a.cz);
   const double cxl = cx[3 * ic], cxd = cx[3 * ic + 1], cxu = cx[3 * ic + 2];
   const bool xper = CYL && a.xper;
   const bool hx_lo = xper || ic > 0, hx_hi = xper || ic + 1 < a.nx;

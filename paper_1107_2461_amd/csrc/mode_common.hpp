@@ -56,6 +56,26 @@ template <> __device__ inline double store_cvt<double>(double x) { return x; }
 template <> __device__ inline float store_cvt<float>(double x) { return static_cast<float>(x); }
 template <> __device__ inline bf16_t store_cvt<bf16_t>(double x) { return f32_to_bf16(static_cast<float>(x)); }
 
+// Pointers into global memory for data whose pointer is itself loaded from memory (the per-RHS
+// tables of a grouped solve): typed in the global address space, so the loads through them are
+// global loads.  A generic pointer would give flat loads, which also hold the LDS counter and so
+// stall every wait on LDS reads behind them.
+template <typename T>
+using gptr_t = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr_t<T> to_global(const T* p) {
+  return (gptr_t<T>)p;
+}
+template <typename V, typename T>
+__device__ inline V gload(gptr_t<T> p) {
+  return *reinterpret_cast<gptr_t<V>>(p);
+}
+// Entry i of a per-RHS pointer table (read as global memory), or `one` without a table.
+template <typename T, typename U>
+__device__ inline gptr_t<T> rhs_ptr(const U* const* tab, long long i, const T* one) {
+  return tab ? to_global(static_cast<const T*>(to_global(tab)[i])) : to_global(one);
+}
+
 // Output layout of the 16x16 MFMA tiles: lane l holds column l % 16; its accumulator
 // register r holds row 4 * (l / 16) + r for the FP32 and BF16 forms but row (l / 16) + 4 r
 // for the FP64 form (measured on gfx950 with a one-wave probe).
@@ -110,8 +130,8 @@ inline int kblock(Prec p) { return p == P_BF16 ? 32 : 16; }
 __device__ inline double column_shift(const EpiArgs& ep, long long n, int r) {
   const int ni = static_cast<int>(n);
   const int by = ni / ep.nx;
-  const double* lx = ep.lamx_rhs ? ep.lamx_rhs[r] : ep.lamx;
-  const double* ly = ep.lamy_rhs ? ep.lamy_rhs[r] : ep.lamy;
+  const gptr_t<double> lx = rhs_ptr(ep.lamx_rhs, r, ep.lamx);
+  const gptr_t<double> ly = rhs_ptr(ep.lamy_rhs, r, ep.lamy);
   return lx[ni - by * ep.nx] + ly[by] + ep.sigma[r];
 }
 // Pointwise divide of eqs. 26-27 with the FP64 denominator lam_z(c) + shift; the exact zero
@@ -210,8 +230,8 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   const int rb0 = wm * MB;
   // grouped solve: the workgroup's columns lie inside one RHS, whose plan gives M and lambda_z
   const long long rg = ep.msw_rhs ? static_cast<long long>(blockIdx.x) * NT / ep.span : 0;
-  const TC* __restrict__ Mp = ep.msw_rhs ? static_cast<const TC*>(ep.msw_rhs[rg]) : Msw;
-  [[maybe_unused]] const double* __restrict__ lamz = ep.lamz_rhs ? ep.lamz_rhs[rg] : ep.lamz;
+  const gptr_t<TC> Mp = rhs_ptr(ep.msw_rhs, rg, Msw);
+  [[maybe_unused]] const gptr_t<double> lamz = rhs_ptr(ep.lamz_rhs, rg, ep.lamz);
   // FP64 divide: lambda_z of every output row staged in LDS before the main loop, so the
   // epilogue reads no global memory between its stores (FP32 keeps the registers of kPre below,
   // measured faster there)
@@ -246,7 +266,7 @@ __global__ __launch_bounds__(256, MINB) void k_left(const TC* __restrict__ Msw, 
   auto load = [&](int kb, vec_t(&a)[MB], TC(&b)[NB][4]) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      a[mb] = *reinterpret_cast<const vec_t*>(Mp + ((static_cast<long long>(rb0 + mb) * KB + kb) * 64 + lane) * 4);
+      a[mb] = gload<vec_t>(Mp + ((static_cast<long long>(rb0 + mb) * KB + kb) * 64 + lane) * 4);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = kb * 16 + 4 * g + s;
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(256, MINB) void k_right(const TC* __restrict__ Msw,
   const long long m0 = mwg + wm * MB * 16;
   const int cb0 = wn * NB;
   // grouped solve: the workgroup's rows lie inside one RHS, whose plan gives M
-  const TC* __restrict__ Mp = ep.msw_rhs ? static_cast<const TC*>(ep.msw_rhs[mwg / ep.span]) : Msw;
+  const gptr_t<TC> Mp = rhs_ptr(ep.msw_rhs, ep.msw_rhs ? mwg / ep.span : 0, Msw);
 
   const TC* rowp[MB];
   bool rowok[MB];
@@ -363,7 +383,7 @@ __global__ __launch_bounds__(256, MINB) void k_right(const TC* __restrict__ Msw,
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      b[nb] = *reinterpret_cast<const vec_t*>(Mp + ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 4);
+      b[nb] = gload<vec_t>(Mp + ((static_cast<long long>(cb0 + nb) * KB + kb) * 64 + lane) * 4);
   };
   if constexpr (PF) load(0, a_cur, b_cur);
   for (int kb = 0; kb < KB; ++kb) {

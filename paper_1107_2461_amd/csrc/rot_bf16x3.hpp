@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   // grouped solve: the tile's rows lie inside one RHS (span = PQ), whose plan gives M and the
   // eigenvalues of the divide
   const long long rg = ep.msw_rhs ? mwg / ep.span : 0;
-  const bf16_t* __restrict__ Mp = ep.msw_rhs ? static_cast<const bf16_t*>(ep.msw_rhs[rg]) : Msw;
+  const gptr_t<bf16_t> Mp = rhs_ptr(ep.msw_rhs, rg, Msw);
 
   // producer assignment: chunk c -> row block c / 64, fragment lane c % 64
   const TIn* src[CPT];
@@ -144,10 +144,10 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
   auto load_b = [&](int kb, u16x8 (&b)[NB][3]) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const bf16_t* base = Mp + (static_cast<long long>(cb0 + nb) * KB + kb) * 512;
-      b[nb][0] = *reinterpret_cast<const u16x8*>(base + lane_off);
-      b[nb][1] = *reinterpret_cast<const u16x8*>(base + piece + lane_off);
-      b[nb][2] = *reinterpret_cast<const u16x8*>(base + 2 * piece + lane_off);
+      const gptr_t<bf16_t> base = Mp + (static_cast<long long>(cb0 + nb) * KB + kb) * 512;
+      b[nb][0] = gload<u16x8>(base + lane_off);
+      b[nb][1] = gload<u16x8>(base + piece + lane_off);
+      b[nb][2] = gload<u16x8>(base + 2 * piece + lane_off);
     }
   };
   // input tiles kb+1 .. kb+DEPTH are in flight in registers while k-block kb is multiplied,
@@ -163,11 +163,11 @@ __global__ __launch_bounds__(256, 2) void k_rot_bf16x3(const bf16_t* __restrict_
       double sv = 1.0;  // rows past the end: never stored
       if (row < Mrows) {
         const long long rr = rhs_of_row(row, r0, PQ);
-        sv = (ep.lamxy_rhs ? ep.lamxy_rhs[rr] : ep.lamxy)[row - rr * PQ] + ep.sigma[rr];
+        sv = rhs_ptr(ep.lamxy_rhs, rr, ep.lamxy)[row - rr * PQ] + ep.sigma[rr];
       }
       sh_shift[i] = sv;
     }
-    const double* __restrict__ lamz = ep.lamz_rhs ? ep.lamz_rhs[rg] : ep.lamz;
+    const gptr_t<double> lamz = rhs_ptr(ep.lamz_rhs, rg, ep.lamz);
     for (int a = tid; a < NLZ; a += 256) sh_lamz[a] = a < K ? lamz[a] : 1.0;
   }
   store_tile(0, stage[0]);
