@@ -9,10 +9,12 @@
 //     out_p = Re( post_p * sum_{q < L} y_q w^{p q} ),  y_q = in_q pre_q (q < N), 0 beyond,
 // one complex DFT of length L = 2M with w = e^{2 pi i / L}: pre_q = e^{i pi A q / M},
 // post_p = s_p e^{i pi (p + A) B / M} (times -i for sines), (A, B) = (alpha, beta) forward and
-// (beta, alpha) inverse, s_p = 1/nu_p forward and 1 inverse.  The DFT is a Stockham
-// auto-sorting FFT over radices 2, 4, 8 (butterflies written out) and 3, 5, 7 (direct sums)
-// in LDS, one workgroup per batch of lines; the tables are built on the host in extended
-// precision.  The z-forward transform can end with the divide of eqs. 26-28.
+// (beta, alpha) inverse, s_p = 1/nu_p forward and 1 inverse.  Two real lines travel in one
+// complex sequence (real and imaginary part) and are separated after the DFT by its conjugate
+// symmetry, so a DFT of length L serves two lines.  The DFT is a Stockham auto-sorting FFT over
+// radices 2, 4, 8 (butterflies written out) and 3, 5, 7 (direct sums) in LDS, one workgroup per
+// batch of lines; the tables are built on the host in extended precision.  The z-forward
+// transform can end with the divide of eqs. 26-28.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,7 +41,7 @@ __device__ __attribute__((always_inline)) inline void dft4(d2& v0, d2& v1, d2& v
   v3 = d02 - d13;
 }
 
-// One Stockham stage of radix R over the B lines of length L held in buf, Ns = product of the
+// One Stockham stage of radix R over the B sequences of length L held in buf, Ns = product of the
 // radices of the earlier stages.  Every thread gathers its butterflies, twiddles them, forms
 // the R-point DFTs in registers, waits for the whole workgroup, then scatters.
 template <int R>
@@ -115,67 +117,100 @@ __device__ __attribute__((always_inline)) inline void stage(d2* buf, int L, int 
   __syncthreads();
 }
 
-// ODD: the plan has radix-3, 5 or 7 stages (their direct sums need about twice the registers
-// of the power-of-two butterflies, so power-of-two lengths use an instantiation without them).
-template <int EPI, bool ODD>
-__global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, double* __restrict__ out, FftTables t,
-                                             FftLines ln, EpiArgs ep) {
-  extern __shared__ d2 buf[];  // B lines of L complex values
-  __shared__ long long lbase[kFftMaxLines];
-  __shared__ double lshift[EPI == EPI_DIVIDE ? kFftMaxLines : 1];
-  const int L = t.L, N = t.N;
-  const int B = t.lines;
-  const long long line0 = static_cast<long long>(blockIdx.x) * B;
-  const int nl = static_cast<int>(min<long long>(B, ln.nlines - line0));
+// Two real lines share one complex sequence: z = (x + i x') pre, Z = DFT(z).  With
+// Y_p = sum_q x_q w^{(p + A) q} (w = e^{2 pi i / L}; pre_q = w^{A q}; 2A an integer) and x real,
+// Y_{L - 2A - p} = conj(Y_p), so Y_p = (Z_p + conj(Z_p')) / 2 and Y'_p = (Z_p - conj(Z_p')) / (2i)
+// with p' = (L - 2A - p) mod L: one FFT serves both lines (the factor 1/2 is in post).
+//
+// Per-line set-up of a batch of B lines starting at line0 (nl of them exist): base offsets and,
+// for the z-forward divide, the line's part lambda_x + lambda_y + sigma of the denominator.
+template <int EPI>
+__device__ __attribute__((always_inline)) inline void fft_lines_setup(const FftLines& ln, const EpiArgs& ep,
+                                                                      long long line0, int nl, long long* lbase,
+                                                                      double* lshift) {
   for (int b = threadIdx.x; b < nl; b += 256) {
     const long long line = line0 + b;
     const long long a0 = line % ln.n0, rest = line / ln.n0;
     const long long a1 = rest % ln.n1, a2 = rest / ln.n1;
     lbase[b] = a2 * ln.t2 + a1 * ln.t1 + a0 * ln.t0;
-    // z-forward: the line is (rhs, y mode, x mode); its part of the eq. 26-27 denominator
+    // z-forward: the line is (rhs, y mode, x mode)
     if constexpr (EPI == EPI_DIVIDE) lshift[b] = ep.lamx[a0] + ep.lamy[a1] + ep.sigma[a2];
   }
+}
+
+// Load of sequence s, element q: z_q = (x_{2s}[q] + i x_{2s+1}[q]) pre_q for q < N, else 0.  A
+// contiguous axis walks along the lines; a strided one walks across adjacent sequences, so the
+// two lines of a sequence (adjacent in memory) and consecutive lanes read consecutive addresses.
+__device__ __attribute__((always_inline)) inline d2 fft_load(const double* __restrict__ in, const FftLines& ln,
+                                                             const long long* lbase, int nl, const d2* pre, int N,
+                                                             int s, int q) {
+  const int b = 2 * s;
+  if (q >= N || b >= nl) return d2{0.0, 0.0};
+  const double x = in[lbase[b] + q * ln.se];
+  const double y = b + 1 < nl ? in[lbase[b + 1] + q * ln.se] : 0.0;
+  const d2 pq = pre[q];
+  return d2{x * pq.x - y * pq.y, x * pq.y + y * pq.x};
+}
+
+// Output p of line b from its sequence's spectrum: Re(post_p Y_p), Y the line's own transform.
+__device__ __attribute__((always_inline)) inline double fft_out(const d2* buf, int L, int refl, const d2* post,
+                                                                int b, int p) {
+  const int base = (b >> 1) * L;
+  int pc = refl - p;
+  if (pc >= L) pc -= L;
+  const d2 Z = buf[fft_lds_index(base + p)], C = buf[fft_lds_index(base + pc)];
+  // first line: (Z + conj(C)) / 2, second: (Z - conj(C)) / (2i); the 1/2 is in post
+  const d2 Y = (b & 1) ? d2{Z.y + C.y, C.x - Z.x} : d2{Z.x + C.x, Z.y - C.y};
+  const d2 ps = post[p];
+  return ps.x * Y.x - ps.y * Y.y;
+}
+
+// ODD: the plan has radix-3, 5 or 7 stages (their direct sums need about twice the registers
+// of the power-of-two butterflies, so power-of-two lengths use an instantiation without them).
+template <int EPI, bool ODD>
+__global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, double* __restrict__ out, FftTables t,
+                                             FftLines ln, EpiArgs ep) {
+  extern __shared__ d2 buf[];  // S sequences of L complex values
+  __shared__ long long lbase[kFftMaxLines];
+  __shared__ double lshift[EPI == EPI_DIVIDE ? kFftMaxLines : 1];
+  const int L = t.L, N = t.N;
+  const int B = t.lines, S = t.lines / 2;
+  const long long line0 = static_cast<long long>(blockIdx.x) * B;
+  const int nl = static_cast<int>(min<long long>(B, ln.nlines - line0));
+  fft_lines_setup<EPI>(ln, ep, line0, nl, lbase, lshift);
   __syncthreads();
   const d2* pre = reinterpret_cast<const d2*>(t.pre);
   const d2* post = reinterpret_cast<const d2*>(t.post);
   const d2* W = reinterpret_cast<const d2*>(t.W);
-  // load and pre-twiddle: a contiguous axis walks each line, a strided one walks across the
-  // adjacent lines of the batch (so consecutive lanes read consecutive addresses)
   const bool contig = ln.se == 1;
-  for (int idx = threadIdx.x; idx < B * L; idx += 256) {
-    int b, q;
+  for (int idx = threadIdx.x; idx < S * L; idx += 256) {
+    int sq, q;
     if (contig) {
-      b = idx / L;
-      q = idx - b * L;
+      sq = idx / L;
+      q = idx - sq * L;
     } else {
-      q = idx / B;
-      b = idx - q * B;
+      q = idx / S;
+      sq = idx - q * S;
     }
-    d2 y = d2{0.0, 0.0};
-    if (q < N && b < nl) {
-      const double x = in[lbase[b] + q * ln.se];
-      const d2 pq = pre[q];
-      y = d2{x * pq.x, x * pq.y};
-    }
-    buf[fft_lds_index(b * L + q)] = y;
+    buf[fft_lds_index(sq * L + q)] = fft_load(in, ln, lbase, nl, pre, N, sq, q);
   }
   __syncthreads();
   int Ns = 1;
-  for (int s = 0; s < t.nst; ++s) {
-    const int r = t.rad[s];
+  for (int st = 0; st < t.nst; ++st) {
+    const int r = t.rad[st];
     if (r == 8) {
-      stage<8>(buf, L, B, Ns, W);
+      stage<8>(buf, L, S, Ns, W);
     } else if (r == 4) {
-      stage<4>(buf, L, B, Ns, W);
+      stage<4>(buf, L, S, Ns, W);
     } else if (r == 2) {
-      stage<2>(buf, L, B, Ns, W);
+      stage<2>(buf, L, S, Ns, W);
     } else if constexpr (ODD) {
       if (r == 3)
-        stage<3>(buf, L, B, Ns, W);
+        stage<3>(buf, L, S, Ns, W);
       else if (r == 5)
-        stage<5>(buf, L, B, Ns, W);
+        stage<5>(buf, L, S, Ns, W);
       else
-        stage<7>(buf, L, B, Ns, W);
+        stage<7>(buf, L, S, Ns, W);
     }
     Ns *= r;
   }
@@ -190,24 +225,22 @@ __global__ __launch_bounds__(256) void k_fft(const double* __restrict__ in, doub
       b = idx - p * B;
     }
     if (b >= nl) continue;
-    const d2 Y = buf[fft_lds_index(b * L + p)];
-    const d2 ps = post[p];
-    double v = ps.x * Y.x - ps.y * Y.y;
+    double v = fft_out(buf, L, t.refl, post, b, p);
     if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);  // p: the z mode (eqs. 26-28)
     out[lbase[b] + p * ln.se] = v;
   }
 }
 
-// ---- power-of-two lengths: L, the lines per workgroup and every stage's radix and stride are
-// compile-time constants, so the index arithmetic has no runtime divisions.
+// ---- power-of-two lengths: L, the sequences per workgroup and every stage's radix and stride
+// are compile-time constants, so the index arithmetic has no runtime divisions.
 template <int L>
-constexpr int pow2_lines() {
-  return kFftBuf / L < kFftMaxLines ? kFftBuf / L : kFftMaxLines;
+constexpr int pow2_seqs() {
+  return kFftBuf / L < kFftMaxLines / 2 ? kFftBuf / L : kFftMaxLines / 2;
 }
 
 template <int R, int L, int Ns>
 __device__ __attribute__((always_inline)) inline void stage_c(d2* buf, const d2* __restrict__ W) {
-  constexpr int B = pow2_lines<L>();
+  constexpr int B = pow2_seqs<L>();
   constexpr int nb = L / R;
   constexpr int total = B * nb;
   constexpr int U = (total + 255) / 256;
@@ -281,39 +314,28 @@ __device__ __attribute__((always_inline)) inline void stages_pow2(d2* buf, const
 template <int EPI, int L>
 __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in, double* __restrict__ out,
                                                   FftTables t, FftLines ln, EpiArgs ep) {
-  constexpr int B = pow2_lines<L>();
-  __shared__ d2 buf[fft_lds_index(B * L - 1) + 1];
+  constexpr int S = pow2_seqs<L>();
+  constexpr int B = 2 * S;
+  __shared__ d2 buf[fft_lds_index(S * L - 1) + 1];
   __shared__ long long lbase[B];
   __shared__ double lshift[EPI == EPI_DIVIDE ? B : 1];
   const int N = t.N;
   const long long line0 = static_cast<long long>(blockIdx.x) * B;
   const int nl = static_cast<int>(min<long long>(B, ln.nlines - line0));
-  if (threadIdx.x < nl) {
-    const long long line = line0 + threadIdx.x;
-    const long long a0 = line % ln.n0, rest = line / ln.n0;
-    const long long a1 = rest % ln.n1, a2 = rest / ln.n1;
-    lbase[threadIdx.x] = a2 * ln.t2 + a1 * ln.t1 + a0 * ln.t0;
-    if constexpr (EPI == EPI_DIVIDE) lshift[threadIdx.x] = ep.lamx[a0] + ep.lamy[a1] + ep.sigma[a2];
-  }
+  fft_lines_setup<EPI>(ln, ep, line0, nl, lbase, lshift);
   __syncthreads();
   const d2* pre = reinterpret_cast<const d2*>(t.pre);
   const d2* post = reinterpret_cast<const d2*>(t.post);
   const d2* W = reinterpret_cast<const d2*>(t.W);
   const bool contig = ln.se == 1;
-  constexpr int UL = (B * L + 255) / 256;
+  constexpr int UL = (S * L + 255) / 256;
 #pragma unroll 4
   for (int u = 0; u < UL; ++u) {
     const int idx = threadIdx.x + 256 * u;
-    if ((B * L) % 256 != 0 && idx >= B * L) break;
-    const int b = contig ? idx / L : idx % B;
-    const int q = contig ? idx % L : idx / B;
-    d2 y = d2{0.0, 0.0};
-    if (q < N && b < nl) {
-      const double x = in[lbase[b] + q * ln.se];
-      const d2 pq = pre[q];
-      y = d2{x * pq.x, x * pq.y};
-    }
-    buf[fft_lds_index(b * L + q)] = y;
+    if ((S * L) % 256 != 0 && idx >= S * L) break;
+    const int sq = contig ? idx / L : idx % S;
+    const int q = contig ? idx % L : idx / S;
+    buf[fft_lds_index(sq * L + q)] = fft_load(in, ln, lbase, nl, pre, N, sq, q);
   }
   __syncthreads();
   stages_pow2<L, 1>(buf, W);
@@ -325,9 +347,7 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
     const int b = contig ? idx / N : idx % B;
     const int p = contig ? idx % N : idx / B;
     if (b >= nl) continue;
-    const d2 Y = buf[fft_lds_index(b * L + p)];
-    const d2 ps = post[p];
-    double v = ps.x * Y.x - ps.y * Y.y;
+    double v = fft_out(buf, L, t.refl, post, b, p);
     if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
     out[lbase[b] + p * ln.se] = v;
   }
@@ -339,7 +359,7 @@ bool launch_pow2(int L, dim3 grid, const double* in, double* out, const FftTable
   switch (L) {
 #define HELM_FFT_CASE(LL)                                                                           \
   case LL:                                                                                          \
-    if (t.lines != pow2_lines<LL>()) return false;                                                  \
+    if (t.lines != 2 * pow2_seqs<LL>()) return false;                                                  \
     hipLaunchKernelGGL((k_fft_pow2<EPI, LL>), grid, dim3(256), 0, st, in, out, t, ln, ep);          \
     return true;
     HELM_FFT_CASE(8)
@@ -432,7 +452,7 @@ bool fft_plan(int sine, double alpha, double beta, int M, int N, bool forward, F
     h.pre[2 * q + 1] = static_cast<double>(std::sin(a));
   }
   for (int p = 0; p < N; ++p) {
-    R sc = 1;
+    R sc = 0.5;  // the 1/2 of the two-lines-per-sequence split
     if (forward) {  // 1 / nu_p, nu_p = sum_j phi_p(j)^2
       R nu = 0;
       for (int j = 0; j < N; ++j) {
@@ -440,7 +460,7 @@ bool fft_plan(int sine, double alpha, double beta, int M, int N, bool forward, F
         const R v = sine ? std::sin(arg) : std::cos(arg);
         nu += v * v;
       }
-      sc = 1 / nu;
+      sc = 0.5 / nu;
     }
     const R a = pi * (p + A) * B / M;
     R re = sc * std::cos(a), im = sc * std::sin(a);
@@ -452,14 +472,19 @@ bool fft_plan(int sine, double alpha, double beta, int M, int N, bool forward, F
     h.post[2 * p] = static_cast<double>(re);
     h.post[2 * p + 1] = static_cast<double>(im);
   }
-  h.lines = kFftBuf / L < kFftMaxLines ? kFftBuf / L : kFftMaxLines;
+  h.lines = 2 * (kFftBuf / L < kFftMaxLines / 2 ? kFftBuf / L : kFftMaxLines / 2);
+  // p' = L - 2A - p needs 2A integral (A = alpha forward, beta inverse: 0, 1/2 or 1)
+  const R twoA = 2 * A;
+  if (twoA != std::floor(twoA) || twoA < 0 || twoA > 2) return false;
+  h.refl = L - static_cast<int>(twoA);
   return true;
 }
 
 hipError_t fft_axis(const double* in, double* out, const FftTables& t, const FftLines& ln, Epi epi,
                     const EpiArgs& ep, hipStream_t st) {
   if (ln.nlines <= 0) return hipSuccess;
-  if (t.L < 2 || t.L > kFftMaxLen || t.lines < 1 || t.lines * t.L > kFftBuf || t.N > t.L / 2 ||
+  if (t.L < 2 || t.L > kFftMaxLen || t.lines < 2 || t.lines % 2 || t.lines > kFftMaxLines ||
+      (t.lines / 2) * t.L > kFftBuf || t.N > t.L / 2 || t.refl < t.L - 2 || t.refl > t.L ||
       t.nst < 1 || t.nst > kFftMaxStages)
     return hipErrorInvalidValue;
   const long long blocks = (ln.nlines + t.lines - 1) / t.lines;
@@ -470,7 +495,7 @@ hipError_t fft_axis(const double* in, double* out, const FftTables& t, const Fft
     if (r != 2 && r != 4 && r != 8 && r != 3 && r != 5 && r != 7) return hipErrorInvalidValue;
     odd = odd || (r & 1);
   }
-  const size_t lds = static_cast<size_t>(fft_lds_index(t.lines * t.L - 1) + 1) * 2 * sizeof(double);
+  const size_t lds = static_cast<size_t>(fft_lds_index((t.lines / 2) * t.L - 1) + 1) * 2 * sizeof(double);
   const dim3 grid(static_cast<unsigned>(blocks)), block(256);
   if (epi != EPI_DIVIDE && epi != EPI_STORE) return hipErrorInvalidValue;
   // power-of-two lengths: the compile-time kernel

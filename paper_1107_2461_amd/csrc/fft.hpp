@@ -12,7 +12,7 @@ namespace helm {
 
 constexpr int kFftMaxLen = 1024;    // L = 2M: axes of up to 512 unknowns
 constexpr int kFftMaxStages = 12;
-constexpr int kFftBuf = 3840;       // complex values per workgroup (lines * L); with the LDS padding
+constexpr int kFftBuf = 2048;       // complex values per workgroup (lines * L); with the LDS padding
                                     // below the batch stays under 64 KB
 // LDS index of element a of a batch: one 16-byte pad every 32 elements and one more every 512,
 // which spreads the strided gathers and scatters of the Stockham stages (and the line-strided
@@ -25,7 +25,9 @@ struct FftTables {
   int L = 0, N = 0, M = 0;      // DFT length 2M; N values in and out per line
   int nst = 0;                  // Stockham stages
   int rad[kFftMaxStages] = {};  // their radices (2, 4, 8, 3, 5, 7)
-  int lines = 1;                // lines per workgroup (kFftBuf / L, at most kFftMaxLines)
+  int lines = 2;                // lines per workgroup: two per complex sequence, kFftBuf / L
+                                // sequences (at most kFftMaxLines lines)
+  int refl = 0;                 // L - 2A: output p of the second line of a pair needs p' = refl - p
   const double* W = nullptr;    // L complex: e^{2 pi i m / L}
   const double* pre = nullptr;  // N complex
   const double* post = nullptr; // N complex: scale, phase and the sine/cosine choice folded in
@@ -33,7 +35,7 @@ struct FftTables {
 
 // Host copy of the tables, built in extended precision.
 struct FftHost {
-  int L = 0, N = 0, M = 0, nst = 0, lines = 1;
+  int L = 0, N = 0, M = 0, nst = 0, lines = 2, refl = 0;
   int rad[kFftMaxStages] = {};
   std::vector<double> W, pre, post;
 };

@@ -179,6 +179,7 @@ helm_status get_axis(int kind, int n, const double* faces, int loc, int lo, int 
         t.M = hs[dir]->M;
         t.nst = hs[dir]->nst;
         t.lines = hs[dir]->lines;
+        t.refl = hs[dir]->refl;
         for (int q = 0; q < t.nst; ++q) t.rad[q] = hs[dir]->rad[q];
         t.W = W;
         t.pre = ps[dir][0];
