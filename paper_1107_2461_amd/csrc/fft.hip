@@ -255,13 +255,33 @@ __device__ __attribute__((always_inline)) inline void stage_c(d2* buf, const d2*
     const int b = t / nb, j = t % nb;
     const int k = j % Ns;
     d2 v[R];
+    // first radix-8 stage: inputs q >= 4 sit at positions >= L / 2, where the zero-padded
+    // sequence is zero (the load phase writes only the first half)
+    constexpr int RIN = (Ns == 1 && R == 8) ? 4 : R;
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = buf[fft_lds_index(b * L + j + q * nb)];
+    for (int q = 0; q < RIN; ++q) v[q] = buf[fft_lds_index(b * L + j + q * nb)];
     if (Ns > 1 && k != 0) {
 #pragma unroll
       for (int q = 1; q < R; ++q) v[q] = cmul(v[q], W[q * k * step]);
     }
-    if constexpr (R == 2) {
+    if constexpr (Ns == 1 && R == 8) {
+      // 4-point DFTs of (v0, v2, 0, 0) and (v1, v3, 0, 0): y_p = a + i^p b
+      const d2 ib2 = mul_i(v[2]), ib3 = mul_i(v[3]);
+      const d2 e0 = v[0] + v[2], e1 = v[0] + ib2, e2 = v[0] - v[2], e3 = v[0] - ib2;
+      const d2 o0 = v[1] + v[3], o1 = v[1] + ib3, o2 = v[1] - v[3], o3 = v[1] - ib3;
+      const double c = 0.70710678118654752440;
+      const d2 t1 = d2{c * (o1.x - o1.y), c * (o1.x + o1.y)};
+      const d2 t2 = mul_i(o2);
+      const d2 t3 = d2{-c * (o3.x + o3.y), c * (o3.x - o3.y)};
+      res[u][0] = e0 + o0;
+      res[u][4] = e0 - o0;
+      res[u][1] = e1 + t1;
+      res[u][5] = e1 - t1;
+      res[u][2] = e2 + t2;
+      res[u][6] = e2 - t2;
+      res[u][3] = e3 + t3;
+      res[u][7] = e3 - t3;
+    } else if constexpr (R == 2) {
       res[u][0] = v[0] + v[1];
       res[u][1] = v[0] - v[1];
     } else if constexpr (R == 4) {
@@ -328,13 +348,16 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
   const d2* post = reinterpret_cast<const d2*>(t.post);
   const d2* W = reinterpret_cast<const d2*>(t.W);
   const bool contig = ln.se == 1;
-  constexpr int UL = (S * L + 255) / 256;
+  // the first half of every sequence (N <= L / 2 values, zeros up to L / 2); the first stage
+  // reads nothing beyond it
+  constexpr int H = L / 2;
+  constexpr int UL = (S * H + 255) / 256;
 #pragma unroll 4
   for (int u = 0; u < UL; ++u) {
     const int idx = threadIdx.x + 256 * u;
-    if ((S * L) % 256 != 0 && idx >= S * L) break;
-    const int sq = contig ? idx / L : idx % S;
-    const int q = contig ? idx % L : idx / S;
+    if ((S * H) % 256 != 0 && idx >= S * H) break;
+    const int sq = contig ? idx / H : idx % S;
+    const int q = contig ? idx % H : idx / S;
     buf[fft_lds_index(sq * L + q)] = fft_load(in, ln, lbase, nl, pre, N, sq, q);
   }
   __syncthreads();
