@@ -331,11 +331,14 @@ __device__ __attribute__((always_inline)) inline void stages_pow2(d2* buf, const
   }
 }
 
-template <int EPI, int L>
+// CONTIG: the axis is the contiguous one (x); otherwise lines are adjacent in memory and the
+// lanes walk across them, each lane stepping its own pointer (no 64-bit multiply per element).
+template <int EPI, int L, bool CONTIG>
 __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in, double* __restrict__ out,
                                                   FftTables t, FftLines ln, EpiArgs ep) {
   constexpr int S = pow2_seqs<L>();
   constexpr int B = 2 * S;
+  constexpr int H = L / 2;  // N <= H values in, N outputs per line
   __shared__ d2 buf[fft_lds_index(S * L - 1) + 1];
   __shared__ long long lbase[B];
   __shared__ double lshift[EPI == EPI_DIVIDE ? B : 1];
@@ -347,32 +350,57 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
   const d2* pre = reinterpret_cast<const d2*>(t.pre);
   const d2* post = reinterpret_cast<const d2*>(t.post);
   const d2* W = reinterpret_cast<const d2*>(t.W);
-  const bool contig = ln.se == 1;
-  // the first half of every sequence (N <= L / 2 values, zeros up to L / 2); the first stage
-  // reads nothing beyond it
-  constexpr int H = L / 2;
-  constexpr int UL = (S * H + 255) / 256;
+  // the first half of every sequence (zeros from N to L / 2); the first stage reads nothing beyond it
+  if constexpr (CONTIG) {
 #pragma unroll 4
-  for (int u = 0; u < UL; ++u) {
-    const int idx = threadIdx.x + 256 * u;
-    if ((S * H) % 256 != 0 && idx >= S * H) break;
-    const int sq = contig ? idx / H : idx % S;
-    const int q = contig ? idx % H : idx / S;
-    buf[fft_lds_index(sq * L + q)] = fft_load(in, ln, lbase, nl, pre, N, sq, q);
+    for (int idx = threadIdx.x; idx < S * H; idx += 256) {
+      const int sq = idx / H, q = idx % H;
+      buf[fft_lds_index(sq * L + q)] = fft_load(in, ln, lbase, nl, pre, N, sq, q);
+    }
+  } else {
+    constexpr int QS = 256 / S;  // elements a lane advances per pass
+    const int sq = threadIdx.x % S, q0 = threadIdx.x / S;
+    const int b = 2 * sq;
+    const bool h0 = b < nl, h1 = b + 1 < nl;
+    const long long step = static_cast<long long>(QS) * ln.se;
+    const double* p0 = in + (h0 ? lbase[b] : 0) + q0 * ln.se;
+    const double* p1 = in + (h1 ? lbase[b + 1] : 0) + q0 * ln.se;
+#pragma unroll 4
+    for (int q = q0; q < H; q += QS, p0 += step, p1 += step) {
+      d2 z = d2{0.0, 0.0};
+      if (q < N && h0) {
+        const double x = *p0;
+        const double y = h1 ? *p1 : 0.0;
+        const d2 pq = pre[q];
+        z = d2{x * pq.x - y * pq.y, x * pq.y + y * pq.x};
+      }
+      buf[fft_lds_index(sq * L + q)] = z;
+    }
   }
   __syncthreads();
   stages_pow2<L, 1>(buf, W);
-  constexpr int US = (B * L / 2 + 255) / 256;  // N <= L / 2 outputs per line
+  if constexpr (CONTIG) {
 #pragma unroll 4
-  for (int u = 0; u < US; ++u) {
-    const int idx = threadIdx.x + 256 * u;
-    if (idx >= B * N) break;
-    const int b = contig ? idx / N : idx % B;
-    const int p = contig ? idx % N : idx / B;
-    if (b >= nl) continue;
-    double v = fft_out(buf, L, t.refl, post, b, p);
-    if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
-    out[lbase[b] + p * ln.se] = v;
+    for (int idx = threadIdx.x; idx < B * H; idx += 256) {
+      const int b = idx / H, p = idx % H;
+      if (p >= N || b >= nl) continue;
+      double v = fft_out(buf, L, t.refl, post, b, p);
+      if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
+      out[lbase[b] + p] = v;
+    }
+  } else {
+    constexpr int PS = 256 / B;  // outputs a lane advances per pass
+    const int b = threadIdx.x % B, p0 = threadIdx.x / B;
+    if (b < nl) {
+      const long long step = static_cast<long long>(PS) * ln.se;
+      double* o = out + lbase[b] + p0 * ln.se;
+#pragma unroll 4
+      for (int p = p0; p < N; p += PS, o += step) {
+        double v = fft_out(buf, L, t.refl, post, b, p);
+        if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
+        *o = v;
+      }
+    }
   }
 }
 
@@ -382,8 +410,11 @@ bool launch_pow2(int L, dim3 grid, const double* in, double* out, const FftTable
   switch (L) {
 #define HELM_FFT_CASE(LL)                                                                           \
   case LL:                                                                                          \
-    if (t.lines != 2 * pow2_seqs<LL>()) return false;                                                  \
-    hipLaunchKernelGGL((k_fft_pow2<EPI, LL>), grid, dim3(256), 0, st, in, out, t, ln, ep);          \
+    if (t.lines != 2 * pow2_seqs<LL>()) return false;                                               \
+    if (ln.se == 1)                                                                                 \
+      hipLaunchKernelGGL((k_fft_pow2<EPI, LL, true>), grid, dim3(256), 0, st, in, out, t, ln, ep);  \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_fft_pow2<EPI, LL, false>), grid, dim3(256), 0, st, in, out, t, ln, ep); \
     return true;
     HELM_FFT_CASE(8)
     HELM_FFT_CASE(16)
