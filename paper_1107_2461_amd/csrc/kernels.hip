@@ -144,8 +144,23 @@ long long thomas_lanes(long long nl) { return (nl + 31) / 32 * 64; }
 int thomas_nseg(int nz) { return (nz / 2 + kSeg - 1) / kSeg; }
 }  // namespace
 
+// Lines of up to kPartMaxN rows, when there are too few of them for two waves per SIMD in the
+// two-sided kernel (fewer than kPartMaxLines lines), use the partitioned kernel below (segments
+// of kPartSeg rows, no checkpoints); otherwise the checkpointed two-sided kernel.  Measured:
+// 128^3 x 3 (49152 lines of 128) 32.0 against 34-37 us; a 256^3 cylinder (65536 radial lines of
+// 256) 81.6 against 77 us, where the two-sided kernel already fills the chip.
+constexpr int kPartSeg = 16;
+constexpr int kPartMaxP = 16;
+constexpr int kPartMaxN = kPartSeg * kPartMaxP;
+constexpr long long kPartMaxLines = 65536;
+
+namespace {
+bool thomas_partitioned(int nz, long long nl) { return nz <= kPartMaxN && nl < kPartMaxLines; }
+}  // namespace
+
 size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs) {
   const long long nl = static_cast<long long>(nx) * ny * nrhs;
+  if (thomas_partitioned(nz, nl)) return 0;
   return static_cast<size_t>(2LL * thomas_nseg(nz) * thomas_lanes(nl)) * sizeof(double);
 }
 
@@ -297,10 +312,179 @@ __global__ __launch_bounds__(64) void k_thomas(double* __restrict__ v, ThomasArg
   }
 }
 
+// Partitioned line solve for lines of up to kPartMaxN rows: each line is cut into P segments of
+// kPartSeg rows, one lane per segment, and a workgroup holds 64 lines x P segments (wave w =
+// segment w of 64 consecutive lines, so every row access of a wave is 64 consecutive values of
+// one plane).  This gives P times the lanes of one chain per line and chains of kPartSeg steps:
+//   1. each segment expresses its first and last unknowns through the unknowns just outside it,
+//      x_first = YF + ZF xL + WF xR and x_last = YL + ZL xL + WL xR, by one elimination from the
+//      top (its pivots kept) and one from the bottom;
+//   2. one lane per line solves the 2P interface equations by a two-term recurrence over the
+//      segments and back-substitution (the reduced system of a diagonally dominant line is
+//      diagonally dominant, so no pivoting);
+//   3. each segment solves its rows with xL and xR known (the top pivots reused).
+// Each value is read once and written once (16 B per point), in place.
+
+template <bool CYL>
+__global__ __launch_bounds__(64 * kPartMaxP) void k_thomas_part(double* __restrict__ v, ThomasArgs a, int P) {
+  extern __shared__ double shm[];
+  const int nz = a.nz;
+  double* sk = shm;                 // K diagonal [nz]
+  double* sv = shm + nz;            // V [nz]
+  double* so = shm + 2 * nz;        // K off-diagonal [nz] (last = 0)
+  double* sg = shm + 3 * nz;        // CYL: the metric G [nz]
+  // [P][6][64] per segment and line: YF ZF WF YL ZL WL, then (step 2) d e al ga and finally
+  // x_first x_last in slots 4 and 5
+  double* red = shm + 4 * nz;
+  for (int i = threadIdx.x; i < nz; i += blockDim.x) {
+    sk[i] = a.kdiag[i];
+    sv[i] = a.vol[i];
+    so[i] = i < nz - 1 ? a.koff[i] : 0.0;
+    if constexpr (CYL) sg[i] = a.gdiag[i];
+  }
+  __syncthreads();
+  const long long Nn = static_cast<long long>(a.nx) * a.ny;
+  const long long nl = Nn * a.nrhs;
+  const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const long long line = static_cast<long long>(blockIdx.x) * 64 + lane;
+  // lanes of absent or skipped lines do no memory access but take part in every barrier
+  bool act = line < nl;
+  const int r = act ? static_cast<int>(line / Nn) : 0;
+  const long long n = act ? line - r * Nn : 0;
+  if (a.skip_null && n == 0) act = false;
+  const int ax = static_cast<int>(n % a.nx), by = static_cast<int>(n / a.nx);
+  const double c = CYL ? a.lamy[by] + a.sigma[r] : a.lamx[ax] + a.lamy[by] + a.sigma[r];
+  const double cg = CYL ? a.lamx[ax] : 0.0;
+  const int lo = seg * kPartSeg;
+  const int len = max(0, min(kPartSeg, nz - lo));
+  double* col = v + static_cast<long long>(r) * nz * Nn + n;
+  auto diag = [&](int i) { return CYL ? sk[i] + c * sv[i] + cg * sg[i] : sk[i] + c * sv[i]; };
+  // the segment's right-hand side V g, all loads issued before the recurrences
+  double rh[kPartSeg];
+#pragma unroll
+  for (int t = 0; t < kPartSeg; ++t) rh[t] = (act && t < len) ? col[static_cast<long long>(lo + t) * Nn] : 0.0;
+#pragma unroll
+  for (int t = 0; t < kPartSeg; ++t) rh[t] *= (t < len) ? sv[lo + t] : 0.0;
+  const double cl = lo > 0 ? so[lo - 1] : 0.0;               // coupling to x_{lo - 1}
+  const double cr = len > 0 ? so[lo + len - 1] : 0.0;        // coupling to x_{lo + len} (0 at the end)
+  // 1a. elimination from the top: pivots (kept), the right-hand side and the left spike
+  double ib[kPartSeg];
+  double y = 0.0, z = 0.0, ibp = 0.0;
+#pragma unroll
+  for (int t = 0; t < kPartSeg; ++t) {
+    if (t < len) {
+      const int i = lo + t;
+      if (t == 0) {
+        ibp = recip(diag(i));
+        y = rh[0];
+        z = -cl;
+      } else {
+        const double mu = so[i - 1] * ibp;
+        ibp = recip(diag(i) - mu * so[i - 1]);
+        y = rh[t] - mu * y;
+        z = -mu * z;
+      }
+    }
+    ib[t] = ibp;
+  }
+  const double YL = y * ibp, ZL = z * ibp, WL = -cr * ibp;
+  // 1b. elimination from the bottom: the right-hand side and the right spike
+  double yb = 0.0, w = 0.0, ibb = 0.0;
+#pragma unroll
+  for (int t = kPartSeg - 1; t >= 0; --t) {
+    if (t < len) {
+      const int i = lo + t;
+      if (t == len - 1) {
+        ibb = recip(diag(i));
+        yb = rh[t];
+        w = -cr;
+      } else {
+        const double mu = so[i] * ibb;
+        ibb = recip(diag(i) - mu * so[i]);
+        yb = rh[t] - mu * yb;
+        w = -mu * w;
+      }
+    }
+  }
+  const double YF = yb * ibb, WF = w * ibb, ZF = -cl * ibb;
+  double* rs = red + (6 * seg) * 64 + lane;
+  rs[0] = YF;
+  rs[64] = ZF;
+  rs[128] = WF;
+  rs[192] = YL;
+  rs[256] = ZL;
+  rs[320] = WL;
+  __syncthreads();
+  // 2. interface unknowns of the line (wave 0): with L_{s-1} = d + e F_s carried,
+  //    F_s = al_s + ga_s F_{s+1}, L_s = d_s + e_s F_{s+1}
+  if (seg == 0) {
+    double d = 0.0, e = 0.0;
+    for (int s2 = 0; s2 < P; ++s2) {
+      const double* q = red + (6 * s2) * 64 + lane;
+      const double yf = q[0], zf = q[64], wf = q[128], yl = q[192], zl = q[256], wl = q[320];
+      const double den = 1.0 / (1.0 - zf * e);
+      const double al = (yf + zf * d) * den, ga = wf * den;
+      const double dn = yl + zl * (d + e * al), en = zl * e * ga + wl;
+      // keep (d, e, al, ga) of segment s2 (its slots are read) for the back-substitution
+      double* o = red + (6 * s2) * 64 + lane;
+      o[0] = dn;
+      o[64] = en;
+      o[128] = al;
+      o[192] = ga;
+      d = dn;
+      e = en;
+    }
+    double F = 0.0;  // F_P: no segment beyond the last
+    for (int s2 = P - 1; s2 >= 0; --s2) {
+      double* o = red + (6 * s2) * 64 + lane;
+      const double L = o[0] + o[64] * F;  // L_s with F_{s+1}
+      F = o[128] + o[192] * F;            // F_s
+      o[256] = F;
+      o[320] = L;
+    }
+  }
+  __syncthreads();
+  // 3. the segment with its outside neighbours known: x_{lo-1} = L_{seg-1}, x_{lo+len} = F_{seg+1}
+  const double xL = seg > 0 ? red[(6 * (seg - 1) + 5) * 64 + lane] : 0.0;
+  const double xR = seg + 1 < P ? red[(6 * (seg + 1) + 4) * 64 + lane] : 0.0;
+  double ys[kPartSeg];
+  double yy = 0.0;
+#pragma unroll
+  for (int t = 0; t < kPartSeg; ++t) {
+    if (t < len) {
+      double rt = rh[t];
+      if (t == 0) rt -= cl * xL;
+      if (t == len - 1) rt -= cr * xR;
+      yy = t == 0 ? rt : rt - so[lo + t - 1] * ib[t - 1] * yy;
+    }
+    ys[t] = yy;
+  }
+  double xn = 0.0;
+#pragma unroll
+  for (int t = kPartSeg - 1; t >= 0; --t) {
+    if (t < len) {
+      const double xt = (t == len - 1) ? ys[t] * ib[t] : (ys[t] - so[lo + t] * xn) * ib[t];
+      if (act) col[static_cast<long long>(lo + t) * Nn] = xt;
+      xn = xt;
+    }
+  }
+}
+
 hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st) {
   const long long nl = static_cast<long long>(a.nx) * a.ny * a.nrhs;
   if (nl == 0) return hipSuccess;
   if (a.nz < 1 || a.nz > 2048) return hipErrorInvalidValue;
+  if (thomas_partitioned(a.nz, nl)) {  // partitioned lines: P segments of kPartSeg rows
+    const int P = (a.nz + kPartSeg - 1) / kPartSeg;
+    const long long blocks = (nl + 63) / 64;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = (4 * static_cast<size_t>(a.nz) + 6 * 64 * static_cast<size_t>(P)) * sizeof(double);
+    if (a.gdiag)
+      hipLaunchKernelGGL(k_thomas_part<true>, dim3(static_cast<unsigned>(blocks)), dim3(64 * P), lds, st, v, a, P);
+    else
+      hipLaunchKernelGGL(k_thomas_part<false>, dim3(static_cast<unsigned>(blocks)), dim3(64 * P), lds, st, v, a, P);
+    return hipGetLastError();
+  }
   const long long blocks = thomas_lanes(nl) / 64;
   const size_t lds = (a.gdiag ? 4 : 3) * static_cast<size_t>(a.nz) * sizeof(double);
   if (a.gdiag)
@@ -313,36 +497,54 @@ hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ singular z line (TPT, all-Neumann)
-__global__ __launch_bounds__(256) void k_null_line(double* __restrict__ v, const double* __restrict__ Ez,
-                                                   const double* __restrict__ Ezinv, const double* __restrict__ lamz,
-                                                   int nx, int ny, int nz, int eq28) {
-  extern __shared__ double sh[];  // 2 * nz
-  double* g = sh;
-  double* gh = sh + nz;
-  const int r = blockIdx.x;
+// The (0, 0) line of every RHS through its eigenbasis: ghat = E^{-1} g, the divide (the zero
+// eigenvalue projected, or eq. 28), u = E ghat.  Two launches spread the two matrix-vector
+// products over many workgroups: one wave per matrix row, its lanes reading the row at
+// consecutive addresses, a fixed shuffle tree summing them.
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ghat[r][c] = (E^{-1} g)_c / lambda_c (0 or the sum itself for lambda_c = 0), c = 4 blockIdx.x + wave
+__global__ __launch_bounds__(256) void k_null_fwd(const double* __restrict__ v, const double* __restrict__ Ezinv,
+                                                  const double* __restrict__ lamz, double* __restrict__ gh, int nx,
+                                                  int ny, int nz, int eq28) {
+  const int r = blockIdx.y;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= nz) return;  // whole waves leave together
   const long long Nn = static_cast<long long>(nx) * ny;
-  double* col = v + static_cast<long long>(r) * nz * Nn;  // line (a, b) = (0, 0)
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) g[k] = col[static_cast<long long>(k) * Nn];
-  __syncthreads();
-  for (int c = threadIdx.x; c < nz; c += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nz; ++k) s += Ezinv[static_cast<long long>(c) * nz + k] * g[k];
+  const double* col = v + static_cast<long long>(r) * nz * Nn;  // line (a, b) = (0, 0)
+  double s = 0.0;
+  for (int k = lane; k < nz; k += 64) s += Ezinv[static_cast<long long>(c) * nz + k] * col[static_cast<long long>(k) * Nn];
+  s = wave_sum(s);
+  if (lane == 0) {
     const double lam = lamz[c];  // the shift of this line is lam_x(0) + lam_y(0) + sigma = 0
-    gh[c] = (lam == 0.0) ? (eq28 ? s : 0.0) : s / lam;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < nz; ++c) s += Ez[static_cast<long long>(k) * nz + c] * gh[c];
-    col[static_cast<long long>(k) * Nn] = s;
+    gh[static_cast<long long>(r) * nz + c] = (lam == 0.0) ? (eq28 ? s : 0.0) : s / lam;
   }
 }
 
+// u[r][k] = (E ghat)_k on the line, k = 4 blockIdx.x + wave
+__global__ __launch_bounds__(256) void k_null_inv(double* __restrict__ v, const double* __restrict__ Ez,
+                                                  const double* __restrict__ gh, int nx, int ny, int nz) {
+  const int r = blockIdx.y;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (k >= nz) return;
+  const long long Nn = static_cast<long long>(nx) * ny;
+  const double* g = gh + static_cast<long long>(r) * nz;
+  double s = 0.0;
+  for (int c = lane; c < nz; c += 64) s += Ez[static_cast<long long>(k) * nz + c] * g[c];
+  s = wave_sum(s);
+  if (lane == 0) v[static_cast<long long>(r) * nz * Nn + static_cast<long long>(k) * Nn] = s;
+}
+
 hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const double* lamz, int nx, int ny, int nz,
-                       int nrhs, int eq28, hipStream_t st) {
+                       int nrhs, int eq28, double* scratch, hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_null_line, dim3(nrhs), dim3(256), 2 * nz * sizeof(double), st, v, Ez, Ezinv, lamz, nx, ny, nz,
-                     eq28);
+  if (!scratch || nrhs > 65535) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((nz + 3) / 4), static_cast<unsigned>(nrhs));
+  hipLaunchKernelGGL(k_null_fwd, grid, dim3(256), 0, st, v, Ezinv, lamz, scratch, nx, ny, nz, eq28);
+  hipLaunchKernelGGL(k_null_inv, grid, dim3(256), 0, st, v, Ez, scratch, nx, ny, nz);
   return hipGetLastError();
 }
 

@@ -108,9 +108,10 @@ size_t thomas_scratch_bytes(int nx, int ny, int nz, int nrhs);
 hipError_t thomas_z(double* v, const ThomasArgs& a, void* chk, hipStream_t st);
 
 // The one singular z line of an all-Neumann Laplace TPT solve: v = E_z diag(1/lam') E_z^{-1} g
-// on the (0, 0) line of every RHS, with 1/lam'_0 = 0 (projection) or 1 (eq. 28).
-hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const double* lamz,
-                       int nx, int ny, int nz, int nrhs, int eq28, hipStream_t st);
+// on the (0, 0) line of every RHS, with 1/lam'_0 = 0 (projection) or 1 (eq. 28).  scratch:
+// nrhs * nz doubles of device memory.
+hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const double* lamz, int nx, int ny, int nz,
+                       int nrhs, int eq28, double* scratch, hipStream_t st);
 
 // 7-point FP64 operator (Kronecker sum of the 1D rows plus sigma):
 //   mode 0: out = H u;  mode 1: out = f - H u (residual);  mode 2: out = f (u unused);

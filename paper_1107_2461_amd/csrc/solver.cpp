@@ -1043,8 +1043,9 @@ helm_status helm::solve_impl(helm_plan* p, const double* f, double* u, int nrhs,
       if (e == hipSuccess) e = timed(p, HELM_STAGE_THOMAS, st, [&] { return thomas_z(u, ta, w + off_b, st); });
       if (e == hipSuccess && all_null)
         e = timed(p, HELM_STAGE_NULL_LINE, st, [&] {
+          // W is free here (Y_FWD consumed it, Y_INV rewrites it): it holds the line's modes
           return null_line_z(u, Z.E, Z.Einv, Z.lam, ta.nx, ta.ny, ta.nz, nrhs,
-                             p->opts.null_mode == HELM_NULL_PAPER_EQ28, st);
+                             p->opts.null_mode == HELM_NULL_PAPER_EQ28, W, st);
         });
       if (e == hipSuccess)
         e = timed(p, HELM_STAGE_Y_INV, st, [&] {
