@@ -165,6 +165,19 @@ __device__ __attribute__((always_inline)) inline double fft_out(const d2* buf, i
   return ps.x * Y.x - ps.y * Y.y;
 }
 
+// Outputs p of both lines of sequence sq (the two spectra share Z_p and Z_p'): Re(post_p Y_p)
+// of the first line in v0, of the second in v1.
+__device__ __attribute__((always_inline)) inline void fft_out2(const d2* buf, int L, int refl, const d2* post, int sq,
+                                                               int p, double& v0, double& v1) {
+  const int base = sq * L;
+  int pc = refl - p;
+  if (pc >= L) pc -= L;
+  const d2 Z = buf[fft_lds_index(base + p)], C = buf[fft_lds_index(base + pc)];
+  const d2 ps = post[p];
+  v0 = ps.x * (Z.x + C.x) - ps.y * (Z.y - C.y);
+  v1 = ps.x * (Z.y + C.y) - ps.y * (C.x - Z.x);
+}
+
 // ODD: the plan has radix-3, 5 or 7 stages (their direct sums need about twice the registers
 // of the power-of-two butterflies, so power-of-two lengths use an instantiation without them).
 template <int EPI, bool ODD>
@@ -379,26 +392,43 @@ __global__ __launch_bounds__(256) void k_fft_pow2(const double* __restrict__ in,
   }
   __syncthreads();
   stages_pow2<L, 1>(buf, W);
+  // each lane finishes output p of both lines of a sequence (one read of Z_p, Z_p' and post_p)
   if constexpr (CONTIG) {
 #pragma unroll 4
-    for (int idx = threadIdx.x; idx < B * H; idx += 256) {
-      const int b = idx / H, p = idx % H;
+    for (int idx = threadIdx.x; idx < S * H; idx += 256) {
+      const int sq = idx / H, p = idx % H;
+      const int b = 2 * sq;
       if (p >= N || b >= nl) continue;
-      double v = fft_out(buf, L, t.refl, post, b, p);
-      if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
-      out[lbase[b] + p] = v;
+      double v0, v1;
+      fft_out2(buf, L, t.refl, post, sq, p, v0, v1);
+      if constexpr (EPI == EPI_DIVIDE) {
+        const double lz = ep.lamz[p];
+        v0 = divide_den(v0, ep, lz + lshift[b]);
+        v1 = divide_den(v1, ep, lz + lshift[b + 1 < nl ? b + 1 : b]);
+      }
+      out[lbase[b] + p] = v0;
+      if (b + 1 < nl) out[lbase[b + 1] + p] = v1;
     }
   } else {
-    constexpr int PS = 256 / B;  // outputs a lane advances per pass
-    const int b = threadIdx.x % B, p0 = threadIdx.x / B;
+    constexpr int PS = 256 / S;  // outputs a lane advances per pass
+    const int sq = threadIdx.x % S, p0 = threadIdx.x / S;
+    const int b = 2 * sq;
     if (b < nl) {
+      const bool h1 = b + 1 < nl;
       const long long step = static_cast<long long>(PS) * ln.se;
-      double* o = out + lbase[b] + p0 * ln.se;
+      double* o0 = out + lbase[b] + p0 * ln.se;
+      double* o1 = out + (h1 ? lbase[b + 1] : lbase[b]) + p0 * ln.se;
 #pragma unroll 4
-      for (int p = p0; p < N; p += PS, o += step) {
-        double v = fft_out(buf, L, t.refl, post, b, p);
-        if constexpr (EPI == EPI_DIVIDE) v = divide_den(v, ep, ep.lamz[p] + lshift[b]);
-        *o = v;
+      for (int p = p0; p < N; p += PS, o0 += step, o1 += step) {
+        double v0, v1;
+        fft_out2(buf, L, t.refl, post, sq, p, v0, v1);
+        if constexpr (EPI == EPI_DIVIDE) {
+          const double lz = ep.lamz[p];
+          v0 = divide_den(v0, ep, lz + lshift[b]);
+          v1 = divide_den(v1, ep, lz + lshift[h1 ? b + 1 : b]);
+        }
+        *o0 = v0;
+        if (h1) *o1 = v1;
       }
     }
   }

@@ -12,12 +12,13 @@ namespace helm {
 
 constexpr int kFftMaxLen = 1024;    // L = 2M: axes of up to 512 unknowns
 constexpr int kFftMaxStages = 12;
-constexpr int kFftBuf = 2048;       // complex values per workgroup (lines * L); with the LDS padding
+constexpr int kFftBuf = 2048;       // complex values per workgroup (sequences * L); with the LDS padding
                                     // below the batch stays under 64 KB
-// LDS index of element a of a batch: one 16-byte pad every 32 elements and one more every 512,
-// which spreads the strided gathers and scatters of the Stockham stages (and the line-strided
-// loads) over the LDS banks: 4 to 8 accesses per 16-byte slot per wave instead of up to 62.
-__host__ __device__ constexpr int fft_lds_index(int a) { return a + (a >> 5) + (a >> 9); }
+// LDS index of element a of a batch: one 16-byte pad every 8 elements and one more every 512.
+// A 16-byte access is served eight lanes at a time, conflict-free when those eight hit distinct
+// 16-byte slots modulo 128 bytes: the first stage's scatter (stride 8 elements) and the
+// sequence-strided loads (stride L) then land on distinct slots.
+__host__ __device__ constexpr int fft_lds_index(int a) { return a + (a >> 3) + (a >> 9); }
 constexpr int kFftMaxLines = 64;
 
 // Device tables of one transform direction of one axis.
