@@ -21,7 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "modes_f64.hip", "modes_f32.hip", "modes_bf16.hip", "modes_bf16x3.hip", "setup.cpp",
            "solver.cpp",
-           "pmatrix.cpp", "server.cpp", "probes.hip", "noalloc.hip", "fft.hip", "timestep.hip"]
+           "pmatrix.cpp", "server.cpp", "devpool.cpp", "probes.hip", "noalloc.hip", "fft.hip", "timestep.hip"]
 
 # Packed-FP32 instructions are disabled for all device code (they have produced silently
 # wrong results on this hardware); hipcc's host pass warns that it ignores the feature.

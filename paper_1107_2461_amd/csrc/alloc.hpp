@@ -13,6 +13,16 @@
 
 namespace helm {
 
+// Blocks of at most kPoolMax bytes without a caller's allocator come from a per-device pool
+// (devpool.cpp): 32 MiB chunks from hipMalloc, kept until the process ends, carved into
+// power-of-two blocks that are recycled through free lists.  hipFree synchronizes the whole
+// device, so freeing a plan's tables directly would make a thread that releases a plan while
+// other solves run (the solve server evicting a resident plan) wait for all of them.  A block
+// is taken on the current device and goes back to that device's pool whichever is current.
+constexpr size_t kPoolMax = size_t(4) << 20;
+hipError_t pool_get(void** p, size_t bytes);
+void pool_put(void* p, size_t bytes);
+
 struct DevAlloc {
   helm_alloc_fn alloc = nullptr;
   helm_free_fn dealloc = nullptr;
@@ -23,7 +33,7 @@ struct DevAlloc {
 
   hipError_t get(void** p, size_t bytes) const {
     if (bytes == 0) bytes = 1;
-    if (!alloc) return hipMalloc(p, bytes);
+    if (!alloc) return bytes <= kPoolMax ? pool_get(p, bytes) : hipMalloc(p, bytes);
     *p = alloc(bytes, ctx);
     if (!*p) return hipErrorOutOfMemory;
     if (reinterpret_cast<uintptr_t>(*p) % 256 != 0) {  // the kernels assume 256-byte alignment
@@ -37,7 +47,10 @@ struct DevAlloc {
     if (!p) return;
     if (bytes == 0) bytes = 1;
     if (!dealloc) {
-      (void)hipFree(p);
+      if (bytes <= kPoolMax)
+        pool_put(p, bytes);
+      else
+        (void)hipFree(p);
       return;
     }
     dealloc(p, bytes, ctx);

@@ -30,5 +30,9 @@ int plan_device(const helm_plan* p);
 // of helm_solve_group, and a shape whose per-RHS extents (ny nz, nz nx, nx ny) are multiples of
 // 512, which every stage's tiling divides.
 bool plans_groupable(const helm_plan* a, const helm_plan* b);
+// Frees a plan without the device-wide synchronization of helm_destroy, for an owner that has
+// already waited for every solve it enqueued with the plan (the solve server: a plan's last
+// reference is dropped after the worker's stream wait).
+void release_plan(helm_plan* p);
 
 }  // namespace helm

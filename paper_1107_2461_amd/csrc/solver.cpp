@@ -615,6 +615,8 @@ void helm_destroy(helm_plan* p) {
 
 }  // extern "C"
 
+void helm::release_plan(helm_plan* p) { delete p; }
+
 namespace {
 
 struct DeviceGuard {
