@@ -843,7 +843,8 @@ def run_serving(torch, args):
     """Serving stream: Poisson arrivals of mixed solve requests through the continuous-batching server."""
     from paper_1107_2461_amd import Server
     n_warm, n_meas = args.serve_warmup, args.serve_requests
-    reqs = workloads.serving_requests(5, n_warm + n_meas, rate_hz=1.0)
+    # warm-up requests, the measured stream, and a second stream for the lower load
+    reqs = workloads.serving_requests(5, n_warm + 2 * n_meas, rate_hz=1.0)
     gen = torch.Generator(device="cuda").manual_seed(5)
     pool = {}
     for g in workloads.SERVING_GRIDS:
@@ -851,22 +852,46 @@ def run_serving(torch, args):
         pool[g] = torch.randn((3, nz, ny, nx), generator=gen, device="cuda", dtype=torch.float64)
     probs = [workloads.serving_problem(r) for r in reqs]
 
+    submit_s, late_s = {}, {}  # per request: duration of the submit call (plan lookup or build), lateness
+    # Output buffers: a ring of 16 per request kind, allocated once; a buffer is handed to a new
+    # request after its previous request has completed (a client reusing its own buffers, not
+    # one allocation per request, which would put the allocator on the timed path).
+    ring = {}
+
     def stream(srv, idx, times):
         """Submit requests idx at relative times (seconds); return the completion records."""
-        outs = {}
         t0 = srv.now()
         recs = []
+        done = set()
         for i, t in zip(idx, times):
             while srv.now() - t0 < t:
                 recs += srv.poll(wait_ms=0)
             r = reqs[i]
             f = pool[tuple(r["n"])][: r["nrhs"]]
-            u = torch.empty_like(f)
-            outs[i] = u
+            slots = ring.setdefault((tuple(r["n"]), r["nrhs"]), {"bufs": [], "owner": [], "next": 0})
+            if len(slots["bufs"]) < 16:
+                slots["bufs"].append(torch.empty_like(f))
+                slots["owner"].append(None)
+                b = len(slots["bufs"]) - 1
+            else:
+                b = slots["next"]
+                slots["next"] = (b + 1) % 16
+                done.update(x["id"] for x in recs)
+                while slots["owner"][b] is not None and slots["owner"][b] not in done:
+                    got = srv.poll(wait_ms=1)
+                    recs += got
+                    done.update(x["id"] for x in got)
+            slots["owner"][b] = i
+            u = slots["bufs"][b]
+            ts = srv.now()
+            late_s[i] = ts - t0 - t
             srv.submit(i, probs[i].faces, f, u, [r["sigma"]] * r["nrhs"], r["bc_lo"], r["bc_hi"])
+            submit_s[i] = srv.now() - ts
             recs += srv.poll(wait_ms=0)
         srv.drain()
         recs += srv.poll(max_records=len(idx) + 16)
+        for sl in ring.values():  # drained: every buffer is free
+            sl["owner"] = [None] * len(sl["owner"])
         return recs
 
     out = {}
@@ -883,10 +908,53 @@ def run_serving(torch, args):
         times = np.cumsum(rng.exponential(1.0 / rate, n_meas))
         idx = list(range(n_warm, n_warm + n_meas))
         recs = stream(srv, idx, times)
+        sub_ms = np.array([submit_s[i] for i in idx]) * 1e3
+        late_ms = np.array([late_s[i] for i in idx]) * 1e3
+        q_ms = np.array([r["t_admit"] - r["t_submit"] for r in recs]) * 1e3
+        svc_ms = np.array([r["t_done"] - r["t_admit"] for r in recs]) * 1e3
+        phases = dict(submit_ms=[float(np.percentile(sub_ms, 50)), float(np.percentile(sub_ms, 99)), float(sub_ms.max())],
+                      late_ms=[float(np.percentile(late_ms, 50)), float(np.percentile(late_ms, 99)), float(late_ms.max())],
+                      queue_ms=[float(np.percentile(q_ms, 50)), float(np.percentile(q_ms, 99)), float(q_ms.max())],
+                      service_ms=[float(np.percentile(svc_ms, 50)), float(np.percentile(svc_ms, 99)),
+                                  float(svc_ms.max())])
+        # the same kind of stream at a lower load (the next n_meas requests of the seeded sequence)
+        low = 0.5
+        idx2 = list(range(n_warm + n_meas, n_warm + 2 * n_meas))
+        times2 = np.cumsum(np.random.default_rng(56).exponential(1.0 / (low * cap), n_meas))
+        recs2 = stream(srv, idx2, times2)
+        # Each request's latency against the same kind of request served alone (grid and RHS
+        # count; three requests of each kind from the stream, each submitted twice with the
+        # server otherwise idle, the second time kept): the slowdown separates queueing and
+        # sharing the GPU from the size mix, which alone spreads the latencies over ~100x.
+        kind = lambda i: (tuple(reqs[i]["n"]), reqs[i]["nrhs"])
+        alone = {}
+        for i in idx:
+            if len(alone.setdefault(kind(i), [])) < 3:
+                alone[kind(i)].append(i)
+        iso = {}
+        for k, ids in alone.items():
+            ms = []
+            for i in ids:
+                for _ in range(2):
+                    rr = stream(srv, [i], [0.0])
+                ms.append(rr[0]["t_done"] - rr[0]["t_submit"])
+            iso[k] = float(np.median(ms))
         stats = srv.stats()
         srv.close()
         bad = [r for r in recs if r["status"] != 0]
         lat = np.array([r["t_done"] - r["t_submit"] for r in recs])
+        slow = np.array([(r["t_done"] - r["t_submit"]) / iso[kind(r["id"])] for r in recs])
+        lat2 = np.array([r["t_done"] - r["t_submit"] for r in recs2])
+        slow2 = np.array([(r["t_done"] - r["t_submit"]) / iso[kind(r["id"])] for r in recs2])
+        at_low = dict(offered_load=low, requests=len(recs2), failed=sum(r["status"] != 0 for r in recs2),
+                      p50_ms=float(np.percentile(lat2, 50) * 1e3), p99_ms=float(np.percentile(lat2, 99) * 1e3),
+                      slowdown_p50=float(np.percentile(slow2, 50)), slowdown_p99=float(np.percentile(slow2, 99)))
+        by_kind = {}
+        for r in recs:
+            by_kind.setdefault(kind(r["id"]), []).append(r["t_done"] - r["t_submit"])
+        kinds = {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/{k[1]}": dict(
+            requests=len(v), alone_ms=iso[k] * 1e3, p50_ms=float(np.percentile(v, 50) * 1e3),
+            p99_ms=float(np.percentile(v, 99) * 1e3)) for k, v in sorted(by_kind.items())}
         wait = np.array([r["t_admit"] - r["t_submit"] for r in recs])
         pts = sum(reqs[r["id"]]["n"][0] * reqs[r["id"]]["n"][1] * reqs[r["id"]]["n"][2] * reqs[r["id"]]["nrhs"]
                   for r in recs)
@@ -894,6 +962,8 @@ def run_serving(torch, args):
         out[prec] = dict(requests=len(recs), failed=len(bad), offered_rate_hz=rate, closed_loop_rate_hz=cap,
                          pts_per_s=pts / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
                          p99_ms=float(np.percentile(lat, 99) * 1e3), mean_queue_ms=float(wait.mean() * 1e3),
+                         slowdown_p50=float(np.percentile(slow, 50)), slowdown_p99=float(np.percentile(slow, 99)),
+                         by_kind=kinds, phases_p50_p99_max=phases, at_lower_load=at_low,
                          mean_sweeps=float(np.mean([r["sweeps"] for r in recs])),
                          plan_hit_rate=stats["plan_hits"] / max(1, stats["plan_hits"] + stats["plan_misses"]),
                          plans_built=stats["plan_misses"],
@@ -910,7 +980,8 @@ def run_serving(torch, args):
                                      "1 or 3 RHS, mixed D/N walls, 20% Laplace",
                             path=best, slots=args.serve_slots, hbm_budget_gb=args.serve_budget_gb,
                             offered_load=args.serve_load),
-                p50_ms=out[best]["p50_ms"], p99_ms=out[best]["p99_ms"], paths=out)
+                p50_ms=out[best]["p50_ms"], p99_ms=out[best]["p99_ms"],
+                slowdown_p50=out[best]["slowdown_p50"], slowdown_p99=out[best]["slowdown_p99"], paths=out)
     print(json.dumps(line))
 
 

@@ -364,17 +364,21 @@ helm_status helm_probe_copy(const void* src, void* dst, long long bytes, void* s
  * finishes a request: queued requests are admitted in arrival order while (a) a solve slot is
  * free and (b) the request's device workspace fits in a free range of the server's workspace
  * arena, which is the whole HBM budget allocated once at creation (through opts->alloc when
- * set); a request that does not fit waits until running requests retire (a later, smaller
+ * set), and (c) if its solve has 2^23 or more unknowns x right-hand sides (big), no other big
+ * solve is running: each kernel of such a solve fills the GPU, so two at once would only share
+ * it while every kernel of the smaller requests running beside them waits behind theirs.  A
+ * request that is not admissible waits until running requests retire (a later admissible
  * request may pass it only if the head has waited less than `max_bypass_ms`).  The server
  * therefore holds exactly the budget in workspace memory and allocates nothing on the device
  * while requests are in flight.  Each slot owns a HIP stream and a host worker thread, so
  * admitted solves run concurrently on the device and new requests are admitted while others
  * are in flight.  Plans (1D eigenbases) are cached on the device by their axis definition and
- * reused across requests.  When a request is admitted, queued requests on the same plan ride
- * along (up to 64 right-hand sides in all, within the budget, passing earlier requests only
- * under the same bypass rule): they are solved as one multi-RHS solve with each request's
- * shifts, their f and u staged through the workspace (2 x 8 bytes per point and right-hand
- * side more), and their records carry the batch size.  Times are seconds since server
+ * reused across requests.  When a request is admitted, queued requests on the same plan, or on
+ * other grids of its shape that a grouped solve (helm_solve_group) can take, ride along (up to
+ * 64 right-hand sides and 2^25 unknowns x right-hand sides in all, below 2^23 while a big solve
+ * runs, within the budget, passing earlier requests only under the same bypass rule): they are
+ * solved as one solve with each request's shifts, their f and u staged through the workspace
+ * (2 x 8 bytes per point and right-hand side more), and their records carry the batch size.  Times are seconds since server
  * creation (steady clock).
  * --------------------------------------------------------------------------------------- */
 typedef struct helm_server helm_server;
@@ -430,11 +434,13 @@ helm_status helm_server_stats(helm_server* s, helm_server_stats_t* out);
 void helm_server_destroy(helm_server* s);
 
 /* Host-only simulation of the admission policy on a virtual clock (no device): n requests
- * with arrival times arrival[i], service times service[i] and footprints foot[i] are
- * scheduled on `slots` slots under `budget`; outputs the admission and completion times.
- * Runs the same admission code as the server.  Errors: EINVAL. */
+ * with arrival times arrival[i], service times service[i], footprints foot[i] and size class
+ * big[i] (nonzero: at least 2^23 unknowns x right-hand sides; big may be NULL, no request big)
+ * are scheduled on `slots` slots under `budget`; outputs the admission and completion times.
+ * Runs the same admission code as the server (riders are not simulated).  Errors: EINVAL. */
 helm_status helm_sched_simulate(int n, const double* arrival, const double* service, const size_t* foot,
-                                int slots, size_t budget, double max_bypass_ms, double* admit, double* done);
+                                const int* big, int slots, size_t budget, double max_bypass_ms, double* admit,
+                                double* done);
 
 /* ---------------------------------------------------------------------------------------
  * Time stepping (Section 5, eqs. 34-40): Boussinesq convection in a box on the MAC grid

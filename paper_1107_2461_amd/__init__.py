@@ -659,17 +659,22 @@ def solve_group(plans, f, nrhs=None, out=None, sigma=None, stream=None, workspac
     return u
 
 
-def sched_simulate(arrival, service, footprint, slots, budget, max_bypass_ms=0.0):
-    """Admission policy of the server on a virtual clock (host only): returns (admit, done) times."""
+def sched_simulate(arrival, service, footprint, slots, budget, max_bypass_ms=0.0, big=None):
+    """Admission policy of the server on a virtual clock (host only): returns (admit, done) times.
+    big: per request, whether its solve is of the big class (at most one runs at a time)."""
     lib = load()
     arr = np.ascontiguousarray(np.asarray(arrival, dtype=np.float64))
     srv = np.ascontiguousarray(np.asarray(service, dtype=np.float64))
     ft = np.ascontiguousarray(np.asarray(footprint, dtype=np.uint64))
     n = len(arr)
+    bg = None if big is None else np.ascontiguousarray(np.asarray(big, dtype=np.int32))
+    if bg is not None and len(bg) != n:
+        raise ValueError("big: one flag per request")
     admit = np.zeros(n)
     done = np.zeros(n)
     check(lib.helm_sched_simulate(n, arr.ctypes.data_as(_lib.DP), srv.ctypes.data_as(_lib.DP),
-                                  ft.ctypes.data_as(C.POINTER(C.c_size_t)), int(slots), int(budget),
+                                  ft.ctypes.data_as(C.POINTER(C.c_size_t)),
+                                  None if bg is None else bg.ctypes.data_as(C.POINTER(C.c_int)), int(slots), int(budget),
                                   float(max_bypass_ms), admit.ctypes.data_as(_lib.DP), done.ctypes.data_as(_lib.DP)),
           "helm_sched_simulate")
     return admit, done

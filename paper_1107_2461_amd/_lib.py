@@ -108,7 +108,8 @@ SIGNATURES = {
     "helm_server_now": (C.c_double, [P]),
     "helm_server_stats": (C.c_int, [P, C.POINTER(HelmServerStats)]),
     "helm_server_destroy": (None, [P]),
-    "helm_sched_simulate": (C.c_int, [C.c_int, DP, DP, C.POINTER(C.c_size_t), C.c_int, C.c_size_t, C.c_double, DP,
+    "helm_sched_simulate": (C.c_int, [C.c_int, DP, DP, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.c_int,
+                                      C.c_size_t, C.c_double, DP,
                                       DP]),
     "helm_cyl_setup": (C.c_int, [C.POINTER(HelmCylGrid), C.POINTER(HelmBC), C.c_double, C.POINTER(HelmOpts),
                                  C.POINTER(P)]),

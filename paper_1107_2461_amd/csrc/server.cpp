@@ -32,22 +32,38 @@
 namespace {
 
 // ---------------------------------------------------------------- admission policy
+// Size classes (unknowns x right-hand sides of one solve).  Each kernel of a solve of
+// kBigPoints or more fills the GPU by itself, so two such solves at once only share it while
+// every kernel of a smaller concurrent request queues behind theirs: at most one big solve
+// runs at a time, and smaller requests may pass a big one that waits for it.  Requests ride
+// along with an admitted one while the solve stays within kBatchPoints: batching pays for
+// small grids, whose launches are short, and past that only lengthens the kernels that every
+// concurrent request waits behind.
+constexpr long long kBigPoints = 1LL << 23;
+constexpr long long kBatchPoints = 1LL << 25;
+
 struct Pending {
   double t_submit;
   size_t foot;
+  bool big;  // at least kBigPoints
 };
 
-// Index (in the arrival-ordered queue) of the next request to admit, or -1.  The head is
-// admitted when it fits; otherwise a later request that fits may pass it only while the head
-// has waited less than max_bypass (after that, capacity is reserved for the head).
+// Index (in the arrival-ordered queue) of the next request to admit, or -1.  A request is
+// admissible when its workspace fits and it is not big while a big solve runs.  The head is
+// admitted when admissible; otherwise a later admissible request may pass it only while the
+// head has waited less than max_bypass (after that, capacity is reserved for the head).
 // fits(foot): whether a workspace of `foot` bytes can be had now.
 template <typename Q, typename Fits>
-int pick_next(const Q& queue, int free_slots, Fits&& fits, double now, double max_bypass) {
+int pick_next(const Q& queue, int free_slots, Fits&& fits, double now, double max_bypass, bool big_running) {
   if (free_slots <= 0 || queue.empty()) return -1;
-  if (fits(queue.front().foot)) return 0;
+  auto ok = [&](size_t i) {
+    const Pending p = queue[i];
+    return fits(p.foot) && !(big_running && p.big);
+  };
+  if (ok(0)) return 0;
   if (now - queue.front().t_submit >= max_bypass) return -1;
   for (size_t i = 1; i < queue.size(); ++i)
-    if (fits(queue[i].foot)) return static_cast<int>(i);
+    if (ok(i)) return static_cast<int>(i);
   return -1;
 }
 
@@ -102,8 +118,12 @@ class Arena {
 
 // Plans are shared between the resident map and the requests that use them; the last owner
 // destroys the plan (an evicted plan stays alive until its queued and running requests finish).
+// Every solve a worker enqueues is waited for before its requests are released, so a plan
+// whose last reference goes has no work in flight: it is freed without helm_destroy's
+// device-wide synchronization, which would stall the submitting thread (evictions happen in
+// submit) behind every running solve.
 using PlanRef = std::shared_ptr<helm_plan>;
-inline PlanRef adopt(helm_plan* p) { return PlanRef(p, [](helm_plan* q) { helm_destroy(q); }); }
+inline PlanRef adopt(helm_plan* p) { return PlanRef(p, [](helm_plan* q) { helm::release_plan(q); }); }
 
 // Resident plans kept per server (least recently used evicted beyond this).  A plan owns no
 // large memory of its own: its 1D eigenbases are shared through the per-axis cache and a split-
@@ -123,6 +143,9 @@ struct Request {
   double* u = nullptr;
   double t_submit = 0.0, t_admit = 0.0;
   size_t foot = 0;  // bytes charged: the solve's workspace (+ staging when others ride along)
+  long long batch_points = 0;  // unknowns x right-hand sides of its solve, riders included
+  bool big = false;            // that solve is of the big class (set at admission)
+  long long points() const { return npts * nrhs; }
   size_t off = 0;   // arena offset of the workspace (set at admission)
   hipEvent_t ready = nullptr;  // recorded on the submitter's stream: f is written
   std::vector<std::unique_ptr<Request>> riders;  // same-plan requests solved with this one
@@ -198,17 +221,21 @@ struct helm_server {
         const std::deque<std::unique_ptr<Request>>& q;
         bool empty() const { return q.empty(); }
         size_t size() const { return q.size(); }
-        Pending operator[](size_t i) const { return {q[i]->t_submit, q[i]->foot}; }
+        Pending operator[](size_t i) const { return {q[i]->t_submit, q[i]->foot, q[i]->points() >= kBigPoints}; }
         Pending front() const { return (*this)[0]; }
       } view{queue};
+      bool big_running = false;
+      for (auto& s : slots) big_running = big_running || (s->job && s->job->big);
       const size_t largest = arena.largest();
       auto fits = [&](size_t foot) { return Arena::round(foot) <= largest; };
-      const int i = pick_next(view, free_slots, fits, now(), max_bypass);
+      const int i = pick_next(view, free_slots, fits, now(), max_bypass, big_running);
       if (i < 0) return;
       std::unique_ptr<Request> r = std::move(queue[i]);
       queue.erase(queue.begin() + i);
       r->t_admit = now();
-      add_riders(r.get(), largest);
+      // beside a running big solve the batch stays below the big class
+      add_riders(r.get(), largest, big_running ? kBigPoints - 1 : kBatchPoints);
+      r->big = r->batch_points >= kBigPoints;
       r->off = arena.take(r->foot);  // fits: checked against the largest free range above
       used += r->foot;
       for (auto& s : slots)
@@ -221,19 +248,21 @@ struct helm_server {
     }
   }
 
-  // Pull queued requests into r's solve while the right-hand sides fit one solve (64) and the
-  // grown footprint fits the budget: requests on r's plan, and requests on other grids of r's
-  // shape that a grouped solve can take (each multiplied by its own plan's eigenbases).  Riders
-  // pass requests queued before them only while the head of the queue has waited less than
+  // Pull queued requests into r's solve while the right-hand sides fit one solve (64), the
+  // solve's unknowns stay within max_points (r alone may exceed it) and the grown footprint
+  // fits the budget: requests on r's plan, and requests on other grids of r's shape that a
+  // grouped solve can take (each multiplied by its own plan's eigenbases).  Riders pass
+  // requests queued before them only while the head of the queue has waited less than
   // max_bypass (or is itself the rider).
-  void add_riders(Request* r, size_t largest) {
+  void add_riders(Request* r, size_t largest, long long max_points) {
     int total = r->nrhs;
+    r->batch_points = r->points();
     const double t = now();
     for (size_t j = 0; j < queue.size();) {
       Request& q = *queue[j];
       const bool head_ok = j == 0 || t - queue.front()->t_submit < max_bypass;
       const bool joins = q.plan == r->plan || helm::plans_groupable(r->plan.get(), q.plan.get());
-      if (!joins || total + q.nrhs > 64 || !head_ok) {
+      if (!joins || total + q.nrhs > 64 || !head_ok || (total + q.nrhs) * r->npts > max_points) {
         ++j;
         continue;
       }
@@ -241,6 +270,7 @@ struct helm_server {
       if (grown == 0 || Arena::round(grown) > largest) break;
       r->foot = grown;
       total += q.nrhs;
+      r->batch_points = total * r->npts;
       queue[j]->t_admit = t;
       r->riders.push_back(std::move(queue[j]));
       queue.erase(queue.begin() + j);
@@ -262,9 +292,11 @@ struct helm_server {
         std::fill(out.begin(), out.end(), HELM_EDEVICE);
         return out;
       }
+    // the stream is waited for whatever the status: a failed solve may have enqueued work
     auto one = [&](Request& q) -> helm_status {
       helm_status st = helm_solve(q.plan.get(), q.f, q.u, q.nrhs, q.sigma.data(), s.ws, s.stream, &info);
-      if (st == HELM_OK && helm::wait_stream(s.stream) != hipSuccess) st = HELM_EDEVICE;
+      const hipError_t we = helm::wait_stream(s.stream);
+      if (st == HELM_OK && we != hipSuccess) st = HELM_EDEVICE;
       return st;
     };
     if (reqs.size() == 1) {
@@ -311,7 +343,8 @@ struct helm_server {
         o += q->nrhs;
       }
     }
-    if ((st == HELM_OK || st == HELM_ENOTCONVERGED) && helm::wait_stream(s.stream) != hipSuccess) st = HELM_EDEVICE;
+    const hipError_t we = helm::wait_stream(s.stream);
+    if ((st == HELM_OK || st == HELM_ENOTCONVERGED) && we != hipSuccess) st = HELM_EDEVICE;
     std::fill(out.begin(), out.end(), st);
     return out;
   }
@@ -537,8 +570,8 @@ extern "C" void helm_server_destroy(helm_server* s) {
 
 // ---------------------------------------------------------------- virtual-clock simulation
 extern "C" helm_status helm_sched_simulate(int n, const double* arrival, const double* service, const size_t* foot,
-                                           int slots, size_t budget, double max_bypass_ms, double* admit,
-                                           double* done) {
+                                           const int* big, int slots, size_t budget, double max_bypass_ms,
+                                           double* admit, double* done) {
   if (n < 0 || slots < 1 || (n > 0 && (!arrival || !service || !foot || !admit || !done))) return HELM_EINVAL;
   for (int i = 0; i < n; ++i) {
     if (foot[i] > budget || !(service[i] >= 0.0)) return HELM_EINVAL;
@@ -549,11 +582,12 @@ extern "C" helm_status helm_sched_simulate(int n, const double* arrival, const d
     std::deque<int> idx;
     const double* arr;
     const size_t* ft;
+    const int* bg;
     bool empty() const { return idx.empty(); }
     size_t size() const { return idx.size(); }
-    Pending operator[](size_t i) const { return {arr[idx[i]], ft[idx[i]]}; }
+    Pending operator[](size_t i) const { return {arr[idx[i]], ft[idx[i]], bg && bg[idx[i]] != 0}; }
     Pending front() const { return (*this)[0]; }
-  } q{{}, arrival, foot};
+  } q{{}, arrival, foot, big};
   std::vector<std::pair<double, int>> running;  // (finish time, request)
   size_t used = 0;
   int next = 0, finished = 0;
@@ -577,7 +611,9 @@ extern "C" helm_status helm_sched_simulate(int n, const double* arrival, const d
     while (next < n && arrival[next] <= now) q.idx.push_back(next++);
     for (;;) {
       auto fits = [&](size_t f) { return used + f <= budget; };
-      const int i = pick_next(q, slots - static_cast<int>(running.size()), fits, now, max_bypass);
+      bool big_running = false;
+      for (auto& r : running) big_running = big_running || (big && big[r.second] != 0);
+      const int i = pick_next(q, slots - static_cast<int>(running.size()), fits, now, max_bypass, big_running);
       if (i < 0) break;
       const int r = q.idx[i];
       q.idx.erase(q.idx.begin() + i);

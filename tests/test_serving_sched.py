@@ -77,3 +77,32 @@ def test_bypass_window_then_no_starvation():
 def test_request_larger_than_budget_is_rejected():
     with pytest.raises(HelmError, match="EINVAL"):
         sched_simulate([0.0], [1.0], [11], 2, 10, 0.0)
+
+
+def test_one_big_solve_at_a_time():
+    # big solves (each fills the GPU) run one after another; small ones arriving meanwhile are
+    # admitted beside the running big one and pass the queued big one within its window
+    arrival = [0.0, 0.0] + list(0.05 + 0.05 * np.arange(10))
+    service = [1.0, 1.0] + [0.02] * 10
+    foot = [1] * 12
+    big = [1, 1] + [0] * 10
+    admit, done = sched_simulate(arrival, service, foot, 4, 100, 2000.0, big=big)
+    assert admit[0] == 0.0 and admit[1] == pytest.approx(done[0])
+    np.testing.assert_allclose(admit[2:], arrival[2:])
+    _check_capacity(admit, done, foot, 4, 100)
+    for t in np.unique(np.concatenate([admit, done])):
+        run = (admit <= t) & (done > t)
+        assert (run & (np.asarray(big) == 1)).sum() <= 1, t
+    # without the size classes the second big one starts at once
+    admit0, _ = sched_simulate(arrival, service, foot, 4, 100, 2000.0)
+    assert admit0[1] == 0.0
+
+
+def test_blocked_big_head_holds_queue_after_window():
+    # with no bypass window a big head that waits for the running big solve is not passed
+    arrival = [0.0, 0.01, 0.02]
+    service = [1.0, 1.0, 0.1]
+    big = [1, 1, 0]
+    admit, done = sched_simulate(arrival, service, [1, 1, 1], 4, 100, 0.0, big=big)
+    assert admit[1] == pytest.approx(done[0])
+    assert admit[2] == pytest.approx(admit[1])
