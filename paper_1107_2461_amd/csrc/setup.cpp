@@ -5,6 +5,8 @@
 #include <cmath>
 #include <limits>
 #include <numeric>
+#include <thread>
+#include <vector>
 
 namespace helm {
 
@@ -201,17 +203,61 @@ void householder_tridiag(int m, std::vector<R> A, std::vector<R>& d, std::vector
   for (int i = 0; i + 1 < m; ++i) e[i] = at(i + 1, i);
 }
 
+// One plane rotation of the QL sweep: columns i and i + 1 of Z become
+// (cs z_i - sn z_{i+1}, sn z_i + cs z_{i+1}).
+template <typename R>
+struct PlaneRot {
+  int i;
+  R cs, sn;
+};
+
+// Z <- Z G_1 G_2 ... (the rotations in the order the sweep made them).  Each row of Z sees
+// the whole sequence independently of the others, so rows are split between threads and
+// taken 16 at a time, each block staying in cache while the rotation list streams past it;
+// every element gets the same operations in the same order as a rotation-by-rotation update.
+template <typename R>
+void apply_rotations(int m, std::vector<R>& Z, const std::vector<PlaneRot<R>>& rots) {
+  constexpr int kRows = 16;
+  auto rows = [&](int k0, int k1) {
+    for (int b = k0; b < k1; b += kRows) {
+      const int b1 = std::min(k1, b + kRows);
+      for (const PlaneRot<R>& g : rots)
+        for (int k = b; k < b1; ++k) {
+          R* zk = &Z[static_cast<size_t>(k) * m];
+          const R f = zk[g.i + 1];
+          zk[g.i + 1] = g.sn * zk[g.i] + g.cs * f;
+          zk[g.i] = g.cs * zk[g.i] - g.sn * f;
+        }
+    }
+  };
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = static_cast<int>(std::min<unsigned>(std::min(hw, 16u), static_cast<unsigned>(m / 32)));
+  if (nt <= 1) {
+    rows(0, m);
+    return;
+  }
+  std::vector<std::thread> pool;
+  const int per = (m + nt - 1) / nt;
+  for (int t = 1; t < nt; ++t)
+    if (t * per < m) pool.emplace_back(rows, t * per, std::min(m, (t + 1) * per));
+  rows(0, std::min(m, per));
+  for (auto& th : pool) th.join();
+}
+
 // Implicit QL with shifts on a symmetric tridiagonal matrix (d: diagonal, e: off-diagonal,
 // e[i] couples i and i + 1), accumulating the rotations into Z (row-major, Z[k][a] =
 // component k of vector a).  On return d holds the eigenvalues in ascending order.
 // keep_z: Z holds an orthogonal basis on entry (a Householder transform) and the rotations
 // are applied to it, so the columns become eigenvectors of the matrix that was reduced.
+// The sweeps record their rotations, which are applied to Z at the end (apply_rotations).
 template <typename R>
 bool tridiag_ql(int m, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Z, bool keep_z = false) {
   if (!keep_z) {
     Z.assign(static_cast<size_t>(m) * m, R(0));
     for (int i = 0; i < m; ++i) Z[static_cast<size_t>(i) * m + i] = R(1);
   }
+  std::vector<PlaneRot<R>> rots;
+  rots.reserve(static_cast<size_t>(m) * m);
   e.resize(m);
   e[m - 1] = R(0);
   const R eps = std::numeric_limits<R>::epsilon();
@@ -252,12 +298,7 @@ bool tridiag_ql(int m, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Z, 
         p = sn * r;
         d[i + 1] = g + p;
         g = cs * r - b;
-        for (int k = 0; k < m; ++k) {
-          R* zk = &Z[static_cast<size_t>(k) * m];
-          f = zk[i + 1];
-          zk[i + 1] = sn * zk[i] + cs * f;
-          zk[i] = cs * zk[i] - sn * f;
-        }
+        rots.push_back({i, cs, sn});
       }
       if (underflow) continue;
       d[l] -= p;
@@ -265,6 +306,7 @@ bool tridiag_ql(int m, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Z, 
       e[s] = R(0);
     }
   }
+  apply_rotations(m, Z, rots);
   // Sort ascending, permuting the eigenvector columns alongside.
   std::vector<int> order(m);
   std::iota(order.begin(), order.end(), 0);

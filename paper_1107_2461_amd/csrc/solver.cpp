@@ -118,8 +118,9 @@ std::string axis_key(int kind, int n, const double* faces, int loc, int lo, int 
   return k;
 }
 
+// build = false: a cache lookup only (out stays empty when the axis is not resident).
 helm_status get_axis(int kind, int n, const double* faces, int loc, int lo, int hi, const DevAlloc& al,
-                     std::shared_ptr<DevAxis>& out) {
+                     std::shared_ptr<DevAxis>& out, bool build = true) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
   const std::string key = axis_key(kind, n, faces, loc, lo, hi, dev, al);
@@ -131,6 +132,7 @@ helm_status get_axis(int kind, int n, const double* faces, int loc, int lo, int 
       if (out) return HELM_OK;
     }
   }
+  if (!build) return HELM_OK;
   auto ax = std::make_shared<DevAxis>();
   ax->device = dev;
   ax->key = key;
@@ -238,6 +240,33 @@ struct DevBuf {
 // that building or dropping a plan on cached axes touches no device memory.
 std::mutex g_pair_mu;
 std::map<std::string, std::weak_ptr<DevBuf>> g_pair_cache;
+
+// The three axes of a plan into ax[0..2]: axis(d, build) is get_axis for plan axis d.  Axes
+// in the cache are taken first; the missing ones (each an eigen-decomposition on the host) are
+// built concurrently, one on the caller's thread and the others on threads of their own that
+// take the caller's device.  Returns the first failure in axis order.
+template <typename F>
+helm_status get_axes(std::shared_ptr<DevAxis>* ax, F&& axis) {
+  helm_status st[3] = {HELM_OK, HELM_OK, HELM_OK};
+  int miss[3], nmiss = 0;
+  for (int d = 0; d < 3; ++d) {
+    if ((st[d] = axis(d, false)) != HELM_OK) return st[d];
+    if (!ax[d]) miss[nmiss++] = d;
+  }
+  if (nmiss == 0) return HELM_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
+  std::vector<std::thread> pool;
+  for (int q = 1; q < nmiss; ++q) {
+    const int d = miss[q];
+    pool.emplace_back([&, d] { st[d] = hipSetDevice(dev) == hipSuccess ? axis(d, true) : HELM_EDEVICE; });
+  }
+  st[miss[0]] = axis(miss[0], true);
+  for (auto& t : pool) t.join();
+  for (helm_status x : st)
+    if (x != HELM_OK) return x;
+  return HELM_OK;
+}
 
 helm_status get_lamxy(const DevAxis& X, const DevAxis& Y, std::shared_ptr<DevBuf>& out) {
   const std::string key = X.key + "|" + Y.key;
@@ -469,12 +498,15 @@ helm_status helm_setup(const helm_grid* grid, const helm_bc* bc, double sigma, c
   p->opts = o;
   p->sigma = sigma;
   if (hipGetDevice(&p->device) != hipSuccess) return HELM_EDEVICE;
+  for (int d = 0; d < 3; ++d)
+    if (!grid->faces[d]) return HELM_EINVAL;
+  const DevAlloc al = DevAlloc::from(o);
+  const helm_status sa = get_axes(p->ax, [&](int d, bool build) {
+    return get_axis(AXIS_CART, grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d], al, p->ax[d], build);
+  });
+  if (sa != HELM_OK) return sa;
   bool alln = true;
   for (int d = 0; d < 3; ++d) {
-    if (!grid->faces[d]) return HELM_EINVAL;
-    const helm_status s = get_axis(AXIS_CART, grid->n[d], grid->faces[d], grid->loc[d], bc->lo[d], bc->hi[d],
-                                   DevAlloc::from(o), p->ax[d]);
-    if (s != HELM_OK) return s;
     p->m[d] = p->ax[d]->host.m;
     alln = alln && p->ax[d]->host.null_mode;
   }
@@ -509,15 +541,17 @@ helm_status helm_cyl_setup(const helm_cyl_grid* grid, const helm_bc* bc, double 
   if (hipGetDevice(&p->device) != hipSuccess) return HELM_EDEVICE;
   const DevAlloc al = DevAlloc::from(o);
   // plan axes: x = theta (fastest), y = z, z = r (slowest: the Thomas direction)
-  helm_status s = grid->theta_periodic
-                      ? get_axis(AXIS_PERIODIC, grid->n[1], grid->faces[1], HELM_CELL, 1, 1, al, p->ax[0])
-                      : get_axis(AXIS_CART, grid->n[1], grid->faces[1], HELM_CELL, bc->lo[1], bc->hi[1], al, p->ax[0]);
+  const helm_status s = get_axes(p->ax, [&](int d, bool build) {
+    if (d == 0)
+      return grid->theta_periodic
+                 ? get_axis(AXIS_PERIODIC, grid->n[1], grid->faces[1], HELM_CELL, 1, 1, al, p->ax[0], build)
+                 : get_axis(AXIS_CART, grid->n[1], grid->faces[1], HELM_CELL, bc->lo[1], bc->hi[1], al, p->ax[0],
+                            build);
+    if (d == 1)
+      return get_axis(AXIS_CART, grid->n[2], grid->faces[2], HELM_CELL, bc->lo[2], bc->hi[2], al, p->ax[1], build);
+    return get_axis(AXIS_RADIAL, grid->n[0], grid->faces[0], HELM_CELL, bc->lo[0], bc->hi[0], al, p->ax[2], build);
+  });
   if (s != HELM_OK) return s;
-  if ((s = get_axis(AXIS_CART, grid->n[2], grid->faces[2], HELM_CELL, bc->lo[2], bc->hi[2], al, p->ax[1])) != HELM_OK)
-    return s;
-  if ((s = get_axis(AXIS_RADIAL, grid->n[0], grid->faces[0], HELM_CELL, bc->lo[0], bc->hi[0], al, p->ax[2])) !=
-      HELM_OK)
-    return s;
   bool alln = true;
   for (int d = 0; d < 3; ++d) {
     p->m[d] = p->ax[d]->host.m;
