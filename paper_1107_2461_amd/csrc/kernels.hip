@@ -556,8 +556,9 @@ hipError_t null_line_z(double* v, const double* Ez, const double* Ezinv, const d
 // indices each) times 4 / wx row segments.  Workgroups are numbered so that each XCD (which
 // receives every 8th workgroup) walks a contiguous range of tiles, y fastest then z: the halo
 // rows and planes a tile shares with its neighbours are then read while they sit in that
-// XCD's L2.  Per point: 8 B of u, 8 B of f in, one value out, plus halo re-reads.
-constexpr int kStencilJS = 4;
+// XCD's L2.  Per point: 8 B of u, 8 B of f in, one value out, plus halo re-reads.  Two rows
+// per lane: one reads the halo rows 3x over, four hold more registers (fewer waves per SIMD).
+constexpr int kStencilJS = 2;
 
 template <typename T>
 __device__ inline T lane_below(T v, int lane) { return __shfl(v, lane > 0 ? lane - 1 : 0); }
