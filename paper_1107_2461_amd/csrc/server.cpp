@@ -21,6 +21,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -436,14 +437,25 @@ extern "C" helm_status helm_server_create(size_t hbm_budget_bytes, int slots, do
   if (s->alloc.get(&mem, s->arena_bytes) != hipSuccess) return HELM_ENOMEM;
   s->arena_mem = static_cast<unsigned char*>(mem);
   s->arena.reset(s->arena_bytes);
+  // from here a failure releases what was made through helm_server_destroy, which takes a
+  // partly built server (no worker, no stream yet)
+  helm_server* raw = s.release();
   for (int k = 0; k < slots; ++k) {
     auto sl = std::make_unique<Slot>();
-    if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) return HELM_EDEVICE;
-    s->slots.push_back(std::move(sl));
+    const bool ok = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess;
+    raw->slots.push_back(std::move(sl));
+    if (!ok) {
+      helm_server_destroy(raw);
+      return HELM_EDEVICE;
+    }
   }
-  helm_server* raw = s.get();
-  for (int k = 0; k < slots; ++k) raw->slots[k]->worker = std::thread([raw, k] { raw->work(k); });
-  *out = s.release();
+  try {
+    for (int k = 0; k < slots; ++k) raw->slots[k]->worker = std::thread([raw, k] { raw->work(k); });
+  } catch (const std::system_error&) {
+    helm_server_destroy(raw);
+    return HELM_ENOMEM;
+  }
+  *out = raw;
   return HELM_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <limits>
 #include <numeric>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -238,8 +239,14 @@ void apply_rotations(int m, std::vector<R>& Z, const std::vector<PlaneRot<R>>& r
   }
   std::vector<std::thread> pool;
   const int per = (m + nt - 1) / nt;
-  for (int t = 1; t < nt; ++t)
-    if (t * per < m) pool.emplace_back(rows, t * per, std::min(m, (t + 1) * per));
+  for (int t = 1; t < nt; ++t) {
+    if (t * per >= m) break;
+    try {
+      pool.emplace_back(rows, t * per, std::min(m, (t + 1) * per));
+    } catch (const std::system_error&) {  // no thread to be had: this range on the caller's
+      rows(t * per, std::min(m, (t + 1) * per));
+    }
+  }
   rows(0, std::min(m, per));
   for (auto& th : pool) th.join();
 }

@@ -17,6 +17,7 @@
 #include <new>
 #include <optional>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -259,7 +260,11 @@ helm_status get_axes(std::shared_ptr<DevAxis>* ax, F&& axis) {
   std::vector<std::thread> pool;
   for (int q = 1; q < nmiss; ++q) {
     const int d = miss[q];
-    pool.emplace_back([&, d] { st[d] = hipSetDevice(dev) == hipSuccess ? axis(d, true) : HELM_EDEVICE; });
+    try {
+      pool.emplace_back([&, d] { st[d] = hipSetDevice(dev) == hipSuccess ? axis(d, true) : HELM_EDEVICE; });
+    } catch (const std::system_error&) {  // no thread to be had: built on the caller's
+      st[d] = axis(d, true);
+    }
   }
   st[miss[0]] = axis(miss[0], true);
   for (auto& t : pool) t.join();
