@@ -324,3 +324,49 @@ def test_plan_memory_from_torch_allocator(torch):
         torch.cuda.synchronize()
         # destroying the plan returns exactly what building it took (other tensors stay)
         assert al.blocks() == b0 and m2 - torch.cuda.memory_allocated() == m1 - m0
+
+
+def test_one_big_solve_at_a_time(torch):
+    """Solves of 2^23 or more unknowns x right-hand sides run one at a time: with eight such
+    requests queued (on 256^3 grids, 1 or 2 RHS, different stretching, so that riders cannot
+    join a 2-RHS head within 2^25) and four slots, no two big solves overlap in time, while the
+    small requests submitted behind them are solved beside them; every big result matches the
+    same request solved alone."""
+    from paper_1107_2461_amd import Plan, Server
+    n = 256
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    big = []
+    for q in range(8):
+        beta = 1.0 + 0.1 * q
+        prob = workloads.box_problem(n, beta, 1.0)
+        f = torch.randn((1 + q % 2, n, n, n), generator=gen, device="cuda", dtype=torch.float64)
+        big.append((prob, f))
+    small = _requests(torch, 12, 31)
+    srv = Server(8 << 30, slots=4, precision="fp64", max_bypass_ms=1000.0)
+    outs = {}
+    torch.cuda.synchronize()
+    for q, (prob, f) in enumerate(big):
+        outs[q] = torch.empty_like(f)
+        srv.submit(q, prob.faces, f, outs[q], [prob.sigma] * f.shape[0], prob.bc_lo, prob.bc_hi)
+    for r, prob, f in small:
+        u = torch.empty_like(f)
+        outs[100 + r["rid"]] = u
+        srv.submit(100 + r["rid"], prob.faces, f, u, [prob.sigma] * f.shape[0], prob.bc_lo, prob.bc_hi)
+    srv.drain()
+    recs = srv.poll(max_records=64)
+    srv.close()
+    assert len(recs) == len(big) + len(small) and all(r["status"] == 0 for r in recs)
+    solves = {}  # one entry per big solve (riders share their head's slot and completion time)
+    for r in recs:
+        if r["id"] < 100:
+            solves.setdefault((r["slot"], r["t_done"]), []).append(r)
+    spans = sorted((min(x["t_admit"] for x in v), max(x["t_done"] for x in v)) for v in solves.values())
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0, ("two big solves overlap", spans)
+    beside = [r for r in recs if r["id"] >= 100 and any(a <= r["t_admit"] < d for a, d in spans)]
+    print(f"big solves {len(spans)}, small requests admitted while a big one ran: {len(beside)} of {len(small)}")
+    for q, (prob, f) in enumerate(big):
+        ref = Plan(prob.faces, prob.bc_lo, prob.bc_hi, prob.sigma).solve(f)
+        torch.cuda.synchronize()
+        d = float((outs[q] - ref).abs().max() / ref.abs().max())
+        assert d <= 1e-12, (q, d)
