@@ -1244,7 +1244,7 @@ def main():
     ap.add_argument("--workload", default="mixed_256",
                     help="mixed_256 (default), multirhs_128, small_32, uniform_256 (use --paths fft,fp64,...), "
                          "cyl_256, pressure, serving, peaks, timestep, shard8")
-    ap.add_argument("--paths", default="fp64,bf16x3_ir,bf16x3_fixed2,fp32_ir,bf16_ir")
+    ap.add_argument("--paths", default="fp64,tpt,bf16x3_ir,bf16x3_fixed2,fp32_ir,bf16_ir")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
