@@ -32,7 +32,11 @@ struct DevicePool {
 
 std::mutex g_pool_mu;
 std::map<int, DevicePool> g_pools;          // by device ordinal; chunks are never returned
-std::unordered_map<void*, int> g_owner;     // block -> the device it was taken on
+struct Owner {
+  int device;  // the device the block was taken on
+  int cls;     // its size class
+};
+std::unordered_map<void*, Owner> g_owner;
 
 }  // namespace
 
@@ -48,7 +52,7 @@ hipError_t pool_get(void** p, size_t bytes) {
   if (!dp.free_[c].empty()) {
     *p = dp.free_[c].back();
     dp.free_[c].pop_back();
-    g_owner[*p] = dev;
+    g_owner[*p] = Owner{dev, c};
     return hipSuccess;
   }
   if (dp.left < sz) {
@@ -68,16 +72,17 @@ hipError_t pool_get(void** p, size_t bytes) {
   *p = dp.cur;
   dp.cur += sz;
   dp.left -= sz;
-  g_owner[*p] = dev;
+  g_owner[*p] = Owner{dev, c};
   return hipSuccess;
 }
 
-void pool_put(void* p, size_t bytes) {
+void pool_put(void* p, size_t) {
   if (!p) return;
   std::lock_guard<std::mutex> lk(g_pool_mu);
   auto it = g_owner.find(p);
   if (it == g_owner.end()) return;  // not a pool block
-  g_pools[it->second].free_[size_class(bytes)].push_back(static_cast<char*>(p));
+  // the block goes back under the class it was taken with, whatever size the caller names
+  g_pools[it->second.device].free_[it->second.cls].push_back(static_cast<char*>(p));
   g_owner.erase(it);
 }
 
