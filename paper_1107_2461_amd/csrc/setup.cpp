@@ -156,15 +156,48 @@ std::string build_operator_periodic(int n, const double* faces, Axis1D& ax) {
 
 namespace {
 
+// Rows [k0, k1) of an m x m row-major matrix through work(k0, k1), split between host threads
+// (the caller's thread takes the first range; a range whose thread cannot be made runs on the
+// caller's): for updates in which every row sees the same sequence of operations.
+template <typename F>
+void split_rows(int m, F&& work) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = static_cast<int>(std::min<unsigned>(std::min(hw, 16u), static_cast<unsigned>(m / 32)));
+  if (nt <= 1) {
+    work(0, m);
+    return;
+  }
+  std::vector<std::thread> pool;
+  const int per = (m + nt - 1) / nt;
+  for (int t = 1; t < nt; ++t) {
+    if (t * per >= m) break;
+    try {
+      pool.emplace_back(work, t * per, std::min(m, (t + 1) * per));
+    } catch (const std::system_error&) {
+      work(t * per, std::min(m, (t + 1) * per));
+    }
+  }
+  work(0, std::min(m, per));
+  for (auto& th : pool) th.join();
+}
+
 // Householder reduction of a dense symmetric matrix A (m x m row-major) to tridiagonal form
 // T = Q^T A Q (Golub & Van Loan, Section 8.3.1): d, e receive the diagonal and off-diagonal of
-// T, Q (row-major) the accumulated orthogonal transform.
+// T, Q (row-major) the accumulated orthogonal transform.  The reflectors are kept and applied
+// to Q at the end, each row of Q taking them in order (split_rows): the same operations per
+// row as accumulating them one by one.
 template <typename R>
 void householder_tridiag(int m, std::vector<R> A, std::vector<R>& d, std::vector<R>& e, std::vector<R>& Q) {
   auto at = [&](int i, int j) -> R& { return A[static_cast<size_t>(i) * m + j]; };
   Q.assign(static_cast<size_t>(m) * m, R(0));
   for (int i = 0; i < m; ++i) Q[static_cast<size_t>(i) * m + i] = R(1);
   std::vector<R> v(m), p(m), w(m);
+  struct Reflector {
+    int k;
+    R beta;
+    std::vector<R> v;  // entries k + 1 .. m - 1
+  };
+  std::vector<Reflector> refl;
   for (int k = 0; k + 2 < m; ++k) {
     // reflector H = I - 2 v v^T / (v^T v) mapping A[k+1.., k] onto a multiple of e_{k+1}
     R alpha = 0;
@@ -190,14 +223,23 @@ void householder_tridiag(int m, std::vector<R> A, std::vector<R>& d, std::vector
     for (int i = k; i < m; ++i) w[i] = p[i] - R(0.5) * beta * vp * v[i];
     for (int i = k; i < m; ++i)
       for (int j = k; j < m; ++j) at(i, j) -= v[i] * w[j] + w[i] * v[j];
-    // Q <- Q H
-    for (int r = 0; r < m; ++r) {
-      R s = 0;
-      for (int j = k + 1; j < m; ++j) s += Q[static_cast<size_t>(r) * m + j] * v[j];
-      s *= beta;
-      for (int j = k + 1; j < m; ++j) Q[static_cast<size_t>(r) * m + j] -= s * v[j];
-    }
+    refl.push_back({k, beta, std::vector<R>(v.begin() + k + 1, v.end())});
   }
+  // Q <- Q H_0 H_1 ...
+  split_rows(m, [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      R* q = &Q[static_cast<size_t>(r) * m];
+      for (const Reflector& h : refl) {
+        const R* vk = h.v.data();  // vk[j - k - 1] = v[j] for j > k
+        R* qk = q + h.k + 1;
+        const int len = m - h.k - 1;
+        R s = 0;
+        for (int j = 0; j < len; ++j) s += qk[j] * vk[j];
+        s *= h.beta;
+        for (int j = 0; j < len; ++j) qk[j] -= s * vk[j];
+      }
+    }
+  });
   d.resize(m);
   e.assign(m, R(0));
   for (int i = 0; i < m; ++i) d[i] = at(i, i);
@@ -219,7 +261,7 @@ struct PlaneRot {
 template <typename R>
 void apply_rotations(int m, std::vector<R>& Z, const std::vector<PlaneRot<R>>& rots) {
   constexpr int kRows = 16;
-  auto rows = [&](int k0, int k1) {
+  split_rows(m, [&](int k0, int k1) {
     for (int b = k0; b < k1; b += kRows) {
       const int b1 = std::min(k1, b + kRows);
       for (const PlaneRot<R>& g : rots)
@@ -230,25 +272,7 @@ void apply_rotations(int m, std::vector<R>& Z, const std::vector<PlaneRot<R>>& r
           zk[g.i] = g.cs * zk[g.i] - g.sn * f;
         }
     }
-  };
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int nt = static_cast<int>(std::min<unsigned>(std::min(hw, 16u), static_cast<unsigned>(m / 32)));
-  if (nt <= 1) {
-    rows(0, m);
-    return;
-  }
-  std::vector<std::thread> pool;
-  const int per = (m + nt - 1) / nt;
-  for (int t = 1; t < nt; ++t) {
-    if (t * per >= m) break;
-    try {
-      pool.emplace_back(rows, t * per, std::min(m, (t + 1) * per));
-    } catch (const std::system_error&) {  // no thread to be had: this range on the caller's
-      rows(t * per, std::min(m, (t + 1) * per));
-    }
-  }
-  rows(0, std::min(m, per));
-  for (auto& th : pool) th.join();
+  });
 }
 
 // Implicit QL with shifts on a symmetric tridiagonal matrix (d: diagonal, e: off-diagonal,
